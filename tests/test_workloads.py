@@ -1,0 +1,65 @@
+"""The seeded input generator: SplitMix64 known answers, determinism,
+counter-based random access, distribution shapes and recorded checksums."""
+import json
+import os
+
+import numpy as np
+
+import workloads as w
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_splitmix64_known_answers():
+    # SplitMix64 started from state 0 (Steele, Lea, Flood 2014): the first
+    # three outputs, as widely reproduced from the published generator
+    expect = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    got = [w.mix64_int((i + 1) * int(w.GAMMA) & ((1 << 64) - 1)) for i in range(3)]
+    assert got == expect
+    arr = w.mix64(np.arange(1, 4, dtype=np.uint64) * w.GAMMA)
+    assert [int(x) for x in arr] == expect
+
+
+def test_counter_based_random_access():
+    full = w.u64_stream(3, 1, 1000)
+    np.testing.assert_array_equal(full[400:700], w.u64_stream(3, 1, 300, start=400))
+    assert not np.array_equal(w.u64_stream(3, 1, 10), w.u64_stream(3, 2, 10))
+    assert not np.array_equal(w.u64_stream(3, 1, 10), w.u64_stream(4, 1, 10))
+
+
+def test_distribution_shapes():
+    n = 1 << 15
+    k = [w.config2_keys(d, n) for d in range(7)]
+    assert all(a.dtype == np.uint32 and a.size == n for a in k)
+    assert k[1].max() < 1024 and k[2].max() < (1 << 16)
+    assert np.all(np.diff(k[3].astype(np.int64)) >= 0)
+    assert np.all(np.diff(k[4].astype(np.int64)) <= 0)
+    inv = np.count_nonzero(np.diff(k[5].astype(np.int64)) < 0)
+    assert 0 < inv <= 2 * (n // 100) * 2
+    np.testing.assert_array_equal(np.sort(k[5]), np.sort(w.uniform_u32(n, 5)))
+    # gaussian clusters: the keys concentrate near at most 16 centres
+    hist = np.bincount((k[6] >> 24).astype(np.int64), minlength=256)
+    assert np.count_nonzero(hist) <= 16 * 2 + 4
+
+
+def test_determinism_and_recorded_checksums():
+    g = json.load(open(os.path.join(HERE, "golden", "input_checksums.json")))
+    n = g["n"]
+    for d, name in enumerate(w.DISTRIBUTIONS):
+        a = w.config2_keys(d, n)
+        np.testing.assert_array_equal(a, w.config2_keys(d, n))
+        assert hex(w.checksum(a)) == g["config2"][name], name
+    for v in ("full", "b40"):
+        k, p = w.config3_pairs(v, n)
+        assert hex(w.checksum(k)) == g["config3"][v]
+        np.testing.assert_array_equal(p, np.arange(n, dtype=np.uint32))
+    sizes, dists = w.segment_plan(64)
+    assert [int(x) for x in sizes] == g["segment_plan_64"]["sizes"]
+    assert [int(x) for x in dists] == g["segment_plan_64"]["dists"]
+    assert sizes.min() >= 16 and sizes.max() < 16 * 65536
+
+
+def test_segmented_keys_layout():
+    keys, off = w.segmented_keys(num_segments=20, lo=16, base=64)
+    assert off.dtype == np.uint64 and off[0] == 0 and int(off[-1]) == keys.size
+    assert np.all(np.diff(off.astype(np.int64)) >= 16)

@@ -1,0 +1,204 @@
+"""Seeded synthetic inputs shaped like the paper's test cases (section 3.1).
+
+This module only makes inputs.  It holds none of the sorting arithmetic, and it
+is the one module that both the GPU library's tests/benchmark and the CPU
+oracle's callers share.
+
+Random numbers come from SplitMix64 (G. Steele, D. Lea, C. Flood, "Fast
+splittable pseudorandom number generators", OOPSLA 2014), used as a
+counter-based generator:
+
+    mix64(z)  = the SplitMix64 output function (two xor-shift-multiply rounds
+                and a final xor-shift, constants from the publication)
+    base(seed, stream) = mix64(seed * GAMMA + stream)          (mod 2^64)
+    value(seed, stream, i) = mix64(base + (i + 1) * GAMMA)     (mod 2^64)
+
+so element i of any stream can be produced independently (and in any order).
+
+Distributions (``DISTRIBUTIONS``), each drawn for n keys from one seed:
+    0 uniform   : r >> 32                       uniform on [0, 2^32)
+    1 small     : r >> 54                       uniform on [0, 1024)
+    2 mid       : r >> 48                       uniform on [0, 2^16)
+    3 sorted    : distribution 0, sorted ascending
+    4 reverse   : distribution 0, sorted descending
+    5 swaps     : distribution 3, then floor(n/100) sequential swaps of
+                  positions i, j = ((r >> 32) * n) >> 32 from stream 1
+    6 gaussian  : 16 cluster means mu_c = r >> 32 (stream 2); key i picks
+                  c = r_i >> 60 (stream 0) and z by Box-Muller from
+                  u1 = ((r >> 11) + 1) / 2^53 (stream 3), u2 = (r >> 11) / 2^53
+                  (stream 4); k = clamp(round(mu_c + 2^20 z), 0, 2^32 - 1),
+                  rounding half away from zero.
+The paper's cases map onto these: case 1 (uniform) -> 0/2, case 2 (sorted)
+-> 3, case 3 (mostly sorted) -> 5, case 4 (small range) -> 1, case 5 (large
+range) -> 0.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_CHUNK = 1 << 22
+
+DISTRIBUTIONS = ("uniform", "small", "mid", "sorted", "reverse", "swaps", "gaussian")
+
+
+def mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on a uint64 array (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def mix64_int(z: int) -> int:
+    """Scalar form of ``mix64`` on Python ints (used for stream bases)."""
+    m = (1 << 64) - 1
+    z &= m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def stream_base(seed: int, stream: int) -> int:
+    return mix64_int((seed * int(GAMMA) + stream) & ((1 << 64) - 1))
+
+
+def u64_stream(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """Elements start .. start+n-1 of the counter-based stream (seed, stream)."""
+    base = np.uint64(stream_base(seed, stream))
+    out = np.empty(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        for lo in range(0, n, _CHUNK):
+            hi = min(n, lo + _CHUNK)
+            ctr = np.arange(start + lo + 1, start + hi + 1, dtype=np.uint64)
+            out[lo:hi] = mix64(base + ctr * GAMMA)
+    return out
+
+
+def _shifted(seed: int, stream: int, n: int, shift: int, dtype) -> np.ndarray:
+    out = np.empty(n, dtype=dtype)
+    for lo in range(0, n, _CHUNK):
+        hi = min(n, lo + _CHUNK)
+        out[lo:hi] = (u64_stream(seed, stream, hi - lo, lo) >> np.uint64(shift)).astype(dtype)
+    return out
+
+
+def uniform_u32(n: int, seed: int) -> np.ndarray:
+    return _shifted(seed, 0, n, 32, np.uint32)
+
+
+def _swaps(a: np.ndarray, seed: int) -> None:
+    n = a.shape[0]
+    m = n // 100
+    if m == 0:
+        return
+    r = u64_stream(seed, 1, 2 * m) >> np.uint64(32)
+    idx = ((r * np.uint64(n)) >> np.uint64(32)).astype(np.int64)
+    # the swaps are sequential by definition; a Python loop keeps that exact
+    for t in range(m):
+        i = idx[2 * t]
+        j = idx[2 * t + 1]
+        a[i], a[j] = a[j], a[i]
+
+
+def _gaussian(n: int, seed: int) -> np.ndarray:
+    mu = (u64_stream(seed, 2, 16) >> np.uint64(32)).astype(np.float64)
+    out = np.empty(n, dtype=np.uint32)
+    two53 = float(1 << 53)
+    for lo in range(0, n, _CHUNK):
+        hi = min(n, lo + _CHUNK)
+        c = (u64_stream(seed, 0, hi - lo, lo) >> np.uint64(60)).astype(np.int64)
+        u1 = ((u64_stream(seed, 3, hi - lo, lo) >> np.uint64(11)).astype(np.float64) + 1.0) / two53
+        u2 = (u64_stream(seed, 4, hi - lo, lo) >> np.uint64(11)).astype(np.float64) / two53
+        z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+        x = mu[c] + float(1 << 20) * z
+        x = np.where(x >= 0, np.floor(x + 0.5), np.ceil(x - 0.5))
+        out[lo:hi] = np.clip(x, 0.0, float((1 << 32) - 1)).astype(np.uint32)
+    return out
+
+
+def config2_keys(dist: int | str, n: int, seed: int | None = None) -> np.ndarray:
+    """n uint32 keys of one of the seven distributions (seed defaults to the
+    distribution index)."""
+    if isinstance(dist, str):
+        dist = DISTRIBUTIONS.index(dist)
+    if seed is None:
+        seed = dist
+    if dist == 0:
+        return uniform_u32(n, seed)
+    if dist == 1:
+        return _shifted(seed, 0, n, 54, np.uint32)
+    if dist == 2:
+        return _shifted(seed, 0, n, 48, np.uint32)
+    if dist in (3, 4, 5):
+        a = np.sort(uniform_u32(n, seed), kind="stable")
+        if dist == 4:
+            a = np.ascontiguousarray(a[::-1])
+        elif dist == 5:
+            _swaps(a, seed)
+        return a
+    if dist == 6:
+        return _gaussian(n, seed)
+    raise ValueError(f"unknown distribution {dist}")
+
+
+def config3_pairs(variant: str, n: int):
+    """uint64 keys (variant 'full': uniform [0, 2^64), seed 0; 'b40': uniform
+    [0, 2^40), seed 1) with the uint32 payload 0..n-1."""
+    if variant == "full":
+        keys = np.empty(n, dtype=np.uint64)
+        for lo in range(0, n, _CHUNK):
+            hi = min(n, lo + _CHUNK)
+            keys[lo:hi] = u64_stream(0, 0, hi - lo, lo)
+    elif variant == "b40":
+        keys = _shifted(1, 0, n, 24, np.uint64)
+    else:
+        raise ValueError(variant)
+    return keys, np.arange(n, dtype=np.uint32)
+
+
+def log_uniform_sizes(count: int, seed: int, lo: int, hi_exp_base: int) -> np.ndarray:
+    """floor(lo * base^u) with u = (r >> 11) / 2^53 from stream 0 of seed."""
+    u = (u64_stream(seed, 0, count) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    return np.floor(lo * np.power(float(hi_exp_base), u)).astype(np.int64)
+
+
+def segment_plan(num_segments: int = 10000, seed: int = 4, lo: int = 16, base: int = 65536):
+    """Sizes (log-uniform in [lo, lo*base)) and distribution index of every
+    segment of the batched workload."""
+    sizes = log_uniform_sizes(num_segments, seed, lo, base)
+    r = u64_stream(seed, 1, num_segments) >> np.uint64(32)
+    dists = ((r * np.uint64(7)) >> np.uint64(32)).astype(np.int64)
+    return sizes, dists
+
+
+def segmented_keys(num_segments: int = 10000, seed: int = 4, lo: int = 16,
+                   base: int = 65536, first_array_seed: int = 1000):
+    """Packed uint32 keys of all segments and the uint64 offsets [S+1]."""
+    sizes, dists = segment_plan(num_segments, seed, lo, base)
+    offsets = np.zeros(num_segments + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(sizes, dtype=np.uint64)
+    keys = np.empty(int(offsets[-1]), dtype=np.uint32)
+    for j in range(num_segments):
+        a, b = int(offsets[j]), int(offsets[j + 1])
+        keys[a:b] = config2_keys(int(dists[j]), b - a, first_array_seed + j)
+    return keys, offsets
+
+
+def checksum(a: np.ndarray) -> int:
+    """Order-dependent 64-bit checksum of an array's bytes, for recording
+    which exact input a run used."""
+    v = np.frombuffer(np.ascontiguousarray(a).tobytes(), dtype=np.uint8)
+    h = 0xCBF29CE484222325
+    # FNV-1a over 8-byte words of the buffer (zero padded), folded with mix64
+    pad = (-v.shape[0]) % 8
+    words = np.frombuffer(np.concatenate([v, np.zeros(pad, np.uint8)]).tobytes(), dtype=np.uint64)
+    idx = np.arange(1, words.shape[0] + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        folded = mix64(words ^ (idx * GAMMA))
+    return mix64_int(h ^ int(np.bitwise_xor.reduce(folded)) if folded.size else h)
