@@ -1,0 +1,243 @@
+/*
+ * intsort.h -- C ABI of an MI355X (gfx950) integer sorting library for the two
+ * methods compared in "Comparison of Bucket Sort and RADIX Sort"
+ * (P. Horsmalahti, arXiv 1206.3511): LSD radix sort (section 2.5,
+ * Algorithm 4, with the counting sort of section 2.4, Algorithm 3, as its
+ * stable digit sort) and bucket sort (section 2.3, Algorithm 2).
+ *
+ * Problem statement (section 2): a call takes a sequence of unsigned
+ * integers and produces the permutation of it that is in nondecreasing
+ * order.  The key-value calls produce the stable permutation: keys that
+ * compare equal keep their input order (section 2, stability), so for every
+ * input exactly one output is correct, and radix and bucket sort return the
+ * same bytes.
+ *
+ * Conventions shared by every call
+ *   - Memory.  Every key, value, offset and workspace pointer is a DEVICE
+ *     pointer on the context's device, owned by the caller.  The library
+ *     owns only the context (host memory).  Sort calls never allocate, never
+ *     synchronise the host with the device and never read device memory back
+ *     to the host: they enqueue kernels on `stream` and return.
+ *   - stream.  A hipStream_t passed as void*; NULL means the null stream.
+ *   - Layout.  Keys are contiguous little-endian uint32 or uint64; values
+ *     are contiguous uint32, one per key.  Input and output base pointers
+ *     must be 16-byte aligned.  keys_in == keys_out (in place) is allowed;
+ *     any other overlap between an input and an output is an error.  The
+ *     same holds for values.
+ *   - Workspace.  A device buffer of at least the size returned by
+ *     intsort_workspace_size() for the same arguments, 256-byte aligned.  Its
+ *     contents on entry do not matter; it must not be used by another call
+ *     that runs at the same time.
+ *   - Errors.  Argument errors are detected on the host and returned before
+ *     anything is enqueued.  A failed kernel launch returns
+ *     INTSORT_ERR_HIP.  Faults during execution surface at the caller's next
+ *     synchronisation of `stream`.  No C++ exception crosses this ABI.
+ *   - Threads.  Calls are reentrant when they use different workspaces.
+ */
+#ifndef INTSORT_H
+#define INTSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum intsort_status {
+    INTSORT_OK = 0,
+    INTSORT_ERR_INVALID_ARGUMENT = 1, /* null pointer with n > 0, bad enum, overlap */
+    INTSORT_ERR_MISALIGNED = 2,       /* a base pointer is not 16-byte aligned */
+    INTSORT_ERR_WORKSPACE_TOO_SMALL = 3,
+    INTSORT_ERR_UNSUPPORTED = 4,      /* option value or size this build does not handle */
+    INTSORT_ERR_OVER_BUDGET = 5,      /* serving: a request larger than the whole budget */
+    INTSORT_ERR_HIP = 6,              /* a HIP runtime call or kernel launch failed */
+    INTSORT_ERR_INTERNAL = 7,
+    INTSORT_ERR_NOT_READY = 8         /* serving: the ticket has not completed yet */
+} intsort_status;
+
+typedef enum intsort_key_type {
+    INTSORT_U32 = 0,
+    INTSORT_U64 = 1
+} intsort_key_type;
+
+typedef enum intsort_algo {
+    INTSORT_RADIX_LSD = 0, /* Algorithm 4 over a stable per-digit counting sort */
+    INTSORT_BUCKET = 1     /* Algorithm 2: range, bucket scatter, per-bucket sort */
+} intsort_algo;
+
+/* option flags */
+#define INTSORT_FLAG_NO_PASS_SKIP 0x1u /* radix: run every digit pass even when
+                                          a digit is the same for all keys */
+
+/*
+ * Options.  A zero field means "library default".
+ *   digit_bits   radix digit width r: 0 (default 8) | 4 | 8 | 11.  The
+ *                number of passes is ceil(key_bits / r) (Algorithm 4's d
+ *                for a key of key_bits bits).
+ *   num_buckets  bucket sort: number of buckets B (default 1024 for u32,
+ *                65536 for u64).  The bucket of key k is
+ *                floor((k - min) * B / (max - min + 1)), exact.
+ *   lds_cutoff   bucket/segmented: segments of at most this many keys are
+ *                sorted by one workgroup entirely in LDS (default: the
+ *                largest size one workgroup holds).
+ *   max_passes   radix: stop after this many digit passes (0 = all).  With a
+ *                value p the output is the input stably sorted on its low
+ *                p*r bits; this exposes the intermediate arrays of
+ *                Algorithm 4.  Implies INTSORT_FLAG_NO_PASS_SKIP.
+ *   flags        INTSORT_FLAG_*.
+ */
+typedef struct intsort_options {
+    uint32_t struct_size; /* sizeof(intsort_options) */
+    uint32_t algo;        /* intsort_algo */
+    uint32_t digit_bits;
+    uint32_t num_buckets;
+    uint32_t lds_cutoff;
+    uint32_t max_passes;
+    uint32_t flags;
+    uint32_t reserved;
+} intsort_options;
+
+typedef struct intsort_ctx intsort_ctx;
+
+/* Human-readable name of a status code; never NULL. */
+const char *intsort_status_string(intsort_status s);
+
+/* Fills *opts with the defaults (radix, 8-bit digits). */
+void intsort_default_options(intsort_options *opts);
+
+/*
+ * Creates a context bound to HIP device `hip_device` (reads its properties;
+ * no device allocation).  *ctx receives the handle; destroy it with
+ * intsort_destroy.  hip_device = -1 makes a planning context that touches no
+ * device: workspace sizes and argument checks work on it, and a sort call
+ * whose arguments pass the checks returns INTSORT_ERR_UNSUPPORTED.
+ */
+intsort_status intsort_create(intsort_ctx **ctx, int hip_device);
+intsort_status intsort_destroy(intsort_ctx *ctx);
+
+/*
+ * Bytes of workspace that a sort of n keys of type kt (with values when
+ * has_values != 0; in num_segments segments for the segmented calls, 0 for
+ * the plain calls) needs under `opts` (NULL = defaults).  The size is
+ * monotone in n and num_segments.
+ */
+intsort_status intsort_workspace_size(const intsort_ctx *ctx, intsort_key_type kt,
+                                      int has_values, uint64_t n, uint64_t num_segments,
+                                      const intsort_options *opts, size_t *bytes);
+
+/*
+ * Sorts n keys (section 2): keys_out receives the nondecreasing permutation
+ * of keys_in.  opts->algo picks radix (section 2.5) or bucket (section 2.3)
+ * sort; both give identical bytes.  n == 0 is a no-op.
+ */
+intsort_status intsort_sort_keys(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in,
+                                 void *keys_out, uint64_t n, const intsort_options *opts,
+                                 void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Stable key-value sort (section 2, stability): keys as intsort_sort_keys,
+ * and vals_out[i] is the value that travelled with keys_out[i]; among equal
+ * keys, values keep their input order.
+ */
+intsort_status intsort_sort_pairs(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in,
+                                  void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                                  uint64_t n, const intsort_options *opts, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+
+/*
+ * Segmented sort: the packed array of n_total keys is split by the device
+ * array d_offsets[num_segments + 1] (uint64, nondecreasing, d_offsets[0] = 0,
+ * d_offsets[num_segments] = n_total; empty segments allowed) and every
+ * segment [d_offsets[s], d_offsets[s+1]) is sorted on its own; nothing moves
+ * between segments.  The offsets live on the device and are not validated
+ * on the host.  Segment starts need no alignment.
+ */
+intsort_status intsort_segmented_sort_keys(intsort_ctx *ctx, intsort_key_type kt,
+                                           const void *keys_in, void *keys_out, uint64_t n_total,
+                                           uint64_t num_segments, const uint64_t *d_offsets,
+                                           const intsort_options *opts, void *workspace,
+                                           size_t workspace_bytes, void *stream);
+
+intsort_status intsort_segmented_sort_pairs(intsort_ctx *ctx, intsort_key_type kt,
+                                            const void *keys_in, void *keys_out,
+                                            const uint32_t *vals_in, uint32_t *vals_out,
+                                            uint64_t n_total, uint64_t num_segments,
+                                            const uint64_t *d_offsets,
+                                            const intsort_options *opts, void *workspace,
+                                            size_t workspace_bytes, void *stream);
+
+/*
+ * Step-level entry points.  Each runs one step of the sorts above on its own
+ * so that the step can be checked against its definition.  Outputs are
+ * device arrays owned by the caller.
+ *
+ * intsort_digit_histogram: counts[p * 2^r + v] = number of keys whose digit p
+ *   ((k >> p*r) & (2^r - 1)) equals v, for every pass p < ceil(key_bits/r),
+ *   from one read of the keys (the count loop of Algorithm 3, for all digits
+ *   at once).  counts is uint32 [passes * 2^r]; n < 2^32.
+ * intsort_minmax: minmax[0] = smallest key, minmax[1] = largest key (as
+ *   uint64, also for 32-bit keys); n >= 1.
+ * intsort_bucket_histogram: counts[b] = number of keys with
+ *   floor((k - min) * B / (max - min + 1)) == b, with min/max read from the
+ *   device array minmax[2] (uint64); counts is uint32 [B].
+ * Each needs a workspace of intsort_workspace_size() for a plain sort of n.
+ */
+intsort_status intsort_digit_histogram(intsort_ctx *ctx, intsort_key_type kt, const void *keys,
+                                       uint64_t n, uint32_t digit_bits, uint32_t *counts,
+                                       void *workspace, size_t workspace_bytes, void *stream);
+intsort_status intsort_minmax(intsort_ctx *ctx, intsort_key_type kt, const void *keys,
+                              uint64_t n, uint64_t *minmax, void *stream);
+intsort_status intsort_bucket_histogram(intsort_ctx *ctx, intsort_key_type kt, const void *keys,
+                                        uint64_t n, const uint64_t *minmax, uint32_t num_buckets,
+                                        uint32_t *counts, void *stream);
+
+/*
+ * Per-kernel timing, for profiling.  intsort_timing_enable(ctx, 1) creates the
+ * HIP events the context needs (host-side objects, no device memory); while
+ * it is on, every sort call on the context records an event on its stream
+ * before its first kernel and after each kernel (up to 1024 events between
+ * reads; later ones are dropped).  intsort_timing_read waits for the last
+ * recorded event and fills out[0..*count) with one entry per kernel launched
+ * since the previous read, in launch order: its kind, its index (the digit
+ * pass for INTSORT_KERNEL_PASS), and the milliseconds between the event
+ * before it and the event after it.  Then it forgets them.  Timing a context
+ * from two threads at once is not supported.
+ */
+typedef enum intsort_kernel_kind {
+    INTSORT_KERNEL_INIT = 0,
+    INTSORT_KERNEL_DIGIT_HISTOGRAM = 1,
+    INTSORT_KERNEL_PASS = 2,
+    INTSORT_KERNEL_COPY = 3,
+    INTSORT_KERNEL_MINMAX = 4,
+    INTSORT_KERNEL_BUCKET_HISTOGRAM = 5,
+    INTSORT_KERNEL_BUCKET_SCATTER = 6,
+    INTSORT_KERNEL_SEGMENT_SORT = 7,
+    INTSORT_KERNEL_PLAN = 8
+} intsort_kernel_kind;
+
+typedef struct intsort_kernel_time {
+    uint32_t kind;  /* intsort_kernel_kind */
+    uint32_t index;
+    float ms;
+} intsort_kernel_time;
+
+intsort_status intsort_timing_enable(intsort_ctx *ctx, int enable);
+intsort_status intsort_timing_read(intsort_ctx *ctx, intsort_kernel_time *out, uint32_t capacity,
+                                   uint32_t *count);
+
+/*
+ * Device-side error word of the last sort that used `workspace`: 0 when no
+ * kernel reported a problem.  A nonzero value means a bounded wait inside a
+ * kernel gave up (the result is then not valid).  Reads device memory, so
+ * it synchronises `stream`.
+ */
+intsort_status intsort_read_device_error(intsort_ctx *ctx, const void *workspace,
+                                         size_t workspace_bytes, uint32_t *error_word,
+                                         void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INTSORT_H */

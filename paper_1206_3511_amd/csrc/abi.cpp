@@ -1,0 +1,458 @@
+// abi.cpp -- the extern "C" entry points declared in include/intsort.h:
+// argument validation on the host, workspace sizing, and dispatch to the
+// kernel launchers.  No C++ exception leaves this file.
+
+#include <hip/hip_runtime.h>
+
+#include <new>
+
+#include "intsort.h"
+#include "internal.hpp"
+#include "sort_plans.hpp"
+
+struct intsort_ctx {
+    int device;
+    int cus;
+    intsort::Timer *timer = nullptr;   // set while per-kernel timing is on
+};
+
+namespace {
+
+using namespace intsort;
+
+int key_bytes_of(intsort_key_type kt) { return kt == INTSORT_U64 ? 8 : 4; }
+
+bool valid_kt(intsort_key_type kt) { return kt == INTSORT_U32 || kt == INTSORT_U64; }
+
+intsort_status read_opts(const intsort_options *in, intsort_key_type kt, intsort_options *out)
+{
+    intsort_default_options(out);
+    if (in) {
+        if (in->struct_size != sizeof(intsort_options)) return INTSORT_ERR_INVALID_ARGUMENT;
+        *out = *in;
+    }
+    if (out->algo != INTSORT_RADIX_LSD && out->algo != INTSORT_BUCKET) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (out->digit_bits == 0) out->digit_bits = 8;
+    if (out->digit_bits != 4 && out->digit_bits != 8 && out->digit_bits != 11) return INTSORT_ERR_UNSUPPORTED;
+    if (out->num_buckets == 0) out->num_buckets = kt == INTSORT_U64 ? 65536u : 1024u;
+    if (out->num_buckets > MAX_BUCKETS) return INTSORT_ERR_UNSUPPORTED;
+    if (out->flags & ~INTSORT_FLAG_NO_PASS_SKIP) return INTSORT_ERR_INVALID_ARGUMENT;
+    return INTSORT_OK;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// true when [a, a+bytes) and [b, b+bytes) intersect without being identical
+bool partial_overlap(const void *a, const void *b, size_t bytes)
+{
+    if (a == b || bytes == 0) return false;
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+intsort_status from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return INTSORT_OK;
+    if (e == hipErrorNotSupported) return INTSORT_ERR_UNSUPPORTED;
+    return INTSORT_ERR_HIP;
+}
+
+// a planning context (device -1) validates and sizes but never launches
+intsort_status set_device(const intsort_ctx *ctx)
+{
+    if (ctx->device < 0) return INTSORT_ERR_UNSUPPORTED;
+    return hipSetDevice(ctx->device) == hipSuccess ? INTSORT_OK : INTSORT_ERR_HIP;
+}
+
+// workspace bytes of a plain (unsegmented) sort
+size_t plain_workspace(int kb, bool pairs, uint64_t n, const intsort_options &o)
+{
+    if (n == 0) return 0;
+    if (o.algo == INTSORT_RADIX_LSD) return radix_layout(kb, pairs, n, (int)o.digit_bits).total;
+    return bucket_layout(kb, pairs, n, o).total;
+}
+
+intsort_status check_ws(const void *ws, size_t ws_bytes, size_t need)
+{
+    if (need == 0) return INTSORT_OK;
+    if (!ws) return INTSORT_ERR_INVALID_ARGUMENT;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return INTSORT_ERR_MISALIGNED;
+    if (ws_bytes < need) return INTSORT_ERR_WORKSPACE_TOO_SMALL;
+    return INTSORT_OK;
+}
+
+intsort_status sort_common(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in, void *keys_out,
+                           const uint32_t *vals_in, uint32_t *vals_out, bool pairs, uint64_t n,
+                           const intsort_options *opts_in, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
+    intsort_options o;
+    intsort_status st = read_opts(opts_in, kt, &o);
+    if (st != INTSORT_OK) return st;
+    if (n == 0) return INTSORT_OK;
+    if (!keys_in || !keys_out) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (pairs && (!vals_in || !vals_out)) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (!aligned16(keys_in) || !aligned16(keys_out)) return INTSORT_ERR_MISALIGNED;
+    if (pairs && (!aligned16(vals_in) || !aligned16(vals_out))) return INTSORT_ERR_MISALIGNED;
+    const int kb = key_bytes_of(kt);
+    if (partial_overlap(keys_in, keys_out, n * (size_t)kb)) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (pairs) {
+        if (partial_overlap(vals_in, vals_out, n * 4)) return INTSORT_ERR_INVALID_ARGUMENT;
+        // keys and values must not share memory at all
+        const void *kbufs[2] = {keys_in, keys_out};
+        const void *vbufs[2] = {vals_in, vals_out};
+        for (auto kp : kbufs)
+            for (auto vp : vbufs) {
+                const uintptr_t k0 = reinterpret_cast<uintptr_t>(kp), v0 = reinterpret_cast<uintptr_t>(vp);
+                if (k0 < v0 + n * 4 && v0 < k0 + n * (size_t)kb) return INTSORT_ERR_INVALID_ARGUMENT;
+            }
+    }
+    if (n > MAX_KEYS) return INTSORT_ERR_UNSUPPORTED;
+    const size_t need = plain_workspace(kb, pairs, n, o);
+    if ((st = check_ws(ws, ws_bytes, need)) != INTSORT_OK) return st;
+    if ((st = set_device(ctx)) != INTSORT_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    if (o.algo == INTSORT_RADIX_LSD) {
+        RadixCall c{};
+        c.keys_in = keys_in;
+        c.keys_out = keys_out;
+        c.vals_in = pairs ? vals_in : nullptr;
+        c.vals_out = pairs ? vals_out : nullptr;
+        c.n = n;
+        c.key_bytes = kb;
+        c.pairs = pairs;
+        c.bits = (int)o.digit_bits;
+        c.L = radix_layout(kb, pairs, n, c.bits);
+        c.max_passes = c.L.g.passes;
+        c.skip_constant_digits = !(o.flags & INTSORT_FLAG_NO_PASS_SKIP);
+        if (o.max_passes != 0) {
+            if ((int)o.max_passes < c.max_passes) c.max_passes = (int)o.max_passes;
+            c.skip_constant_digits = false;
+        }
+        c.ws = static_cast<char *>(ws);
+        c.timer = ctx->timer;
+        return from_hip(radix_sort_run(c, s));
+    }
+    BucketCall b{};
+    b.keys_in = keys_in;
+    b.keys_out = keys_out;
+    b.vals_in = pairs ? vals_in : nullptr;
+    b.vals_out = pairs ? vals_out : nullptr;
+    b.n = n;
+    b.key_bytes = kb;
+    b.pairs = pairs;
+    b.opts = o;
+    b.L = bucket_layout(kb, pairs, n, o);
+    b.ws = static_cast<char *>(ws);
+    return from_hip(bucket_sort_run(b, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *intsort_status_string(intsort_status s)
+{
+    switch (s) {
+    case INTSORT_OK: return "ok";
+    case INTSORT_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case INTSORT_ERR_MISALIGNED: return "misaligned pointer";
+    case INTSORT_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case INTSORT_ERR_UNSUPPORTED: return "unsupported option or size";
+    case INTSORT_ERR_OVER_BUDGET: return "request exceeds the memory budget";
+    case INTSORT_ERR_HIP: return "HIP runtime error";
+    case INTSORT_ERR_INTERNAL: return "internal error";
+    case INTSORT_ERR_NOT_READY: return "not ready";
+    }
+    return "unknown status";
+}
+
+void intsort_default_options(intsort_options *o)
+{
+    if (!o) return;
+    *o = intsort_options{};
+    o->struct_size = sizeof(intsort_options);
+    o->algo = INTSORT_RADIX_LSD;
+    o->digit_bits = 8;
+}
+
+intsort_status intsort_create(intsort_ctx **ctx, int hip_device)
+{
+    try {
+        if (!ctx) return INTSORT_ERR_INVALID_ARGUMENT;
+        *ctx = nullptr;
+        if (hip_device < -1) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (hip_device >= 0) {
+            int count = 0;
+            if (hipGetDeviceCount(&count) != hipSuccess) return INTSORT_ERR_HIP;
+            if (hip_device >= count) return INTSORT_ERR_INVALID_ARGUMENT;
+        }
+        intsort_ctx *c = new (std::nothrow) intsort_ctx;
+        if (!c) return INTSORT_ERR_INTERNAL;
+        c->device = hip_device;
+        c->cus = hip_device >= 0 ? device_cu_count(hip_device) : 0;
+        *ctx = c;
+        return INTSORT_OK;
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_timing_enable(intsort_ctx *ctx, int enable)
+{
+    try {
+        if (!ctx) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (enable && !ctx->timer) {
+            if (ctx->device < 0) return INTSORT_ERR_UNSUPPORTED;
+            intsort_status st = set_device(ctx);
+            if (st != INTSORT_OK) return st;
+            Timer *t = new (std::nothrow) Timer;
+            if (!t) return INTSORT_ERR_INTERNAL;
+            for (int i = 0; i < Timer::CAP; i++) {
+                if (hipEventCreate(&t->ev[i]) != hipSuccess) {
+                    for (int j = 0; j < i; j++) (void)hipEventDestroy(t->ev[j]);
+                    delete t;
+                    return INTSORT_ERR_HIP;
+                }
+            }
+            ctx->timer = t;
+        } else if (!enable && ctx->timer) {
+            for (int i = 0; i < Timer::CAP; i++) (void)hipEventDestroy(ctx->timer->ev[i]);
+            delete ctx->timer;
+            ctx->timer = nullptr;
+        }
+        return INTSORT_OK;
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_timing_read(intsort_ctx *ctx, intsort_kernel_time *out, uint32_t capacity, uint32_t *count)
+{
+    try {
+        if (!ctx || !count || (capacity > 0 && !out)) return INTSORT_ERR_INVALID_ARGUMENT;
+        Timer *t = ctx->timer;
+        *count = 0;
+        if (!t || t->used == 0) return INTSORT_OK;
+        if (hipEventSynchronize(t->ev[t->used - 1]) != hipSuccess) return INTSORT_ERR_HIP;
+        uint32_t m = 0;
+        for (int i = 1; i < t->used && m < capacity; i++) {
+            if (t->kind[i] == Timer::CALL_START) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, t->ev[i - 1], t->ev[i]) != hipSuccess) return INTSORT_ERR_HIP;
+            out[m].kind = t->kind[i];
+            out[m].index = t->index[i];
+            out[m].ms = ms;
+            m++;
+        }
+        *count = m;
+        t->used = 0;
+        return INTSORT_OK;
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_destroy(intsort_ctx *ctx)
+{
+    if (ctx && ctx->timer) intsort_timing_enable(ctx, 0);
+    delete ctx;
+    return INTSORT_OK;
+}
+
+intsort_status intsort_workspace_size(const intsort_ctx *ctx, intsort_key_type kt, int has_values, uint64_t n,
+                                      uint64_t num_segments, const intsort_options *opts, size_t *bytes)
+{
+    try {
+        if (!ctx || !bytes || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
+        intsort_options o;
+        intsort_status st = read_opts(opts, kt, &o);
+        if (st != INTSORT_OK) return st;
+        if (n > MAX_KEYS) return INTSORT_ERR_UNSUPPORTED;
+        const int kb = key_bytes_of(kt);
+        size_t plain = plain_workspace(kb, has_values != 0, n, o);
+        // the step entry points share the plain layout's counters
+        if (plain == 0) plain = radix_layout(kb, false, 1, (int)o.digit_bits).total;
+        if (num_segments == 0) {
+            *bytes = plain;
+        } else {
+            if (num_segments > MAX_SEGMENTS) return INTSORT_ERR_UNSUPPORTED;
+            *bytes = segmented_layout(kb, has_values != 0, n, num_segments, o).total;
+        }
+        return INTSORT_OK;
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_sort_keys(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in, void *keys_out,
+                                 uint64_t n, const intsort_options *opts, void *workspace,
+                                 size_t workspace_bytes, void *stream)
+{
+    try {
+        return sort_common(ctx, kt, keys_in, keys_out, nullptr, nullptr, false, n, opts, workspace,
+                           workspace_bytes, stream);
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_sort_pairs(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in, void *keys_out,
+                                  const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
+                                  const intsort_options *opts, void *workspace, size_t workspace_bytes,
+                                  void *stream)
+{
+    try {
+        return sort_common(ctx, kt, keys_in, keys_out, vals_in, vals_out, true, n, opts, workspace,
+                           workspace_bytes, stream);
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+static intsort_status segmented_common(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in,
+                                       void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                                       bool pairs, uint64_t n_total, uint64_t num_segments,
+                                       const uint64_t *d_offsets, const intsort_options *opts_in, void *ws,
+                                       size_t ws_bytes, void *stream)
+{
+    if (!ctx || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
+    intsort_options o;
+    intsort_status st = read_opts(opts_in, kt, &o);
+    if (st != INTSORT_OK) return st;
+    if (n_total == 0 || num_segments == 0) return INTSORT_OK;
+    if (!d_offsets || !keys_in || !keys_out) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (pairs && (!vals_in || !vals_out)) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (!aligned16(keys_in) || !aligned16(keys_out)) return INTSORT_ERR_MISALIGNED;
+    if (pairs && (!aligned16(vals_in) || !aligned16(vals_out))) return INTSORT_ERR_MISALIGNED;
+    const int kb = key_bytes_of(kt);
+    if (partial_overlap(keys_in, keys_out, n_total * (size_t)kb)) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (pairs && partial_overlap(vals_in, vals_out, n_total * 4)) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (n_total > MAX_KEYS || num_segments > MAX_SEGMENTS) return INTSORT_ERR_UNSUPPORTED;
+    const SegLayout L = segmented_layout(kb, pairs, n_total, num_segments, o);
+    if ((st = check_ws(ws, ws_bytes, L.total)) != INTSORT_OK) return st;
+    if ((st = set_device(ctx)) != INTSORT_OK) return st;
+    SegCall c{};
+    c.keys_in = keys_in;
+    c.keys_out = keys_out;
+    c.vals_in = pairs ? vals_in : nullptr;
+    c.vals_out = pairs ? vals_out : nullptr;
+    c.n = n_total;
+    c.num_segments = num_segments;
+    c.offsets = d_offsets;
+    c.key_bytes = kb;
+    c.pairs = pairs;
+    c.opts = o;
+    c.L = L;
+    c.ws = static_cast<char *>(ws);
+    return from_hip(segmented_sort_run(c, static_cast<hipStream_t>(stream)));
+}
+
+intsort_status intsort_segmented_sort_keys(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in,
+                                           void *keys_out, uint64_t n_total, uint64_t num_segments,
+                                           const uint64_t *d_offsets, const intsort_options *opts,
+                                           void *workspace, size_t workspace_bytes, void *stream)
+{
+    try {
+        return segmented_common(ctx, kt, keys_in, keys_out, nullptr, nullptr, false, n_total, num_segments,
+                                d_offsets, opts, workspace, workspace_bytes, stream);
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_segmented_sort_pairs(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in,
+                                            void *keys_out, const uint32_t *vals_in, uint32_t *vals_out,
+                                            uint64_t n_total, uint64_t num_segments, const uint64_t *d_offsets,
+                                            const intsort_options *opts, void *workspace,
+                                            size_t workspace_bytes, void *stream)
+{
+    try {
+        return segmented_common(ctx, kt, keys_in, keys_out, vals_in, vals_out, true, n_total, num_segments,
+                                d_offsets, opts, workspace, workspace_bytes, stream);
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_digit_histogram(intsort_ctx *ctx, intsort_key_type kt, const void *keys, uint64_t n,
+                                       uint32_t digit_bits, uint32_t *counts, void *workspace,
+                                       size_t workspace_bytes, void *stream)
+{
+    try {
+        if (!ctx || !valid_kt(kt) || !counts) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (digit_bits != 4 && digit_bits != 8 && digit_bits != 11) return INTSORT_ERR_UNSUPPORTED;
+        if (n > 0 && !keys) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (n > 0 && !aligned16(keys)) return INTSORT_ERR_MISALIGNED;
+        if (n >= (1ull << 32)) return INTSORT_ERR_UNSUPPORTED;
+        const int kb = key_bytes_of(kt);
+        RadixCall c{};
+        c.keys_in = keys;
+        c.n = n;
+        c.key_bytes = kb;
+        c.bits = (int)digit_bits;
+        c.L = radix_layout(kb, false, n > 0 ? n : 1, c.bits);
+        c.max_passes = c.L.g.passes;
+        intsort_status st = check_ws(workspace, workspace_bytes, (size_t)CTR_WORDS * 4);
+        if (st != INTSORT_OK) return st;
+        if ((st = set_device(ctx)) != INTSORT_OK) return st;
+        c.ws = static_cast<char *>(workspace);
+        return from_hip(digit_histogram_run(c, counts, static_cast<hipStream_t>(stream)));
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_minmax(intsort_ctx *ctx, intsort_key_type kt, const void *keys, uint64_t n,
+                              uint64_t *minmax, void *stream)
+{
+    try {
+        if (!ctx || !valid_kt(kt) || !minmax || n == 0 || !keys) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (!aligned16(keys)) return INTSORT_ERR_MISALIGNED;
+        intsort_status st = set_device(ctx);
+        if (st != INTSORT_OK) return st;
+        return from_hip(minmax_run(key_bytes_of(kt), keys, n, minmax, static_cast<hipStream_t>(stream)));
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_bucket_histogram(intsort_ctx *ctx, intsort_key_type kt, const void *keys, uint64_t n,
+                                        const uint64_t *minmax, uint32_t num_buckets, uint32_t *counts,
+                                        void *stream)
+{
+    try {
+        if (!ctx || !valid_kt(kt) || !minmax || !counts || num_buckets == 0) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (n > 0 && !keys) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (num_buckets > MAX_BUCKETS || n >= (1ull << 32)) return INTSORT_ERR_UNSUPPORTED;
+        intsort_status st = set_device(ctx);
+        if (st != INTSORT_OK) return st;
+        return from_hip(bucket_histogram_run(key_bytes_of(kt), keys, n, minmax, num_buckets, counts,
+                                             static_cast<hipStream_t>(stream)));
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_read_device_error(intsort_ctx *ctx, const void *workspace, size_t workspace_bytes,
+                                         uint32_t *error_word, void *stream)
+{
+    try {
+        if (!ctx || !workspace || !error_word) return INTSORT_ERR_INVALID_ARGUMENT;
+        // every workspace layout starts with the counters block
+        const size_t at = (size_t)CTR_ERROR * 4;
+        if (workspace_bytes < (size_t)CTR_WORDS * 4) return INTSORT_ERR_INVALID_ARGUMENT;
+        intsort_status st = set_device(ctx);
+        if (st != INTSORT_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (hipMemcpyAsync(error_word, static_cast<const char *>(workspace) + at, 4, hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+            return INTSORT_ERR_HIP;
+        return from_hip(hipStreamSynchronize(s));
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+}  // extern "C"

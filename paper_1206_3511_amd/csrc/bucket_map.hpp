@@ -1,0 +1,86 @@
+// bucket_map.hpp -- the exact bucket index of bucket sort on the device.
+//
+// Bucket sort (section 2.3, Algorithm 2) sends key A[i] to bucket n*A[i]/M
+// for keys in [0, M].  With the value range measured instead of assumed and
+// B buckets, the bucket of key k is
+//     b(k) = floor((k - min) * B / R),   R = max - min + 1,
+// which is nondecreasing in k, maps min to 0 and stays below B.  The product
+// (k - min) * B needs 52 bits for 32-bit keys and up to 84 bits for 64-bit
+// keys, and R can be 2^64.  A double-precision quotient gives an estimate that
+// is at most one away from b(k); exact integer arithmetic then corrects it, so
+// the result is exact for every key.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace intsort {
+
+struct BucketMap {
+    uint64_t mn;
+    uint64_t range_m1;    // R - 1 = max - min (R itself may be 2^64)
+    uint32_t buckets;     // B >= 1
+    double scale;         // B / R in double precision
+    bool full64;          // R == 2^64
+};
+
+__device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, uint32_t B)
+{
+    BucketMap m;
+    m.mn = mn;
+    m.range_m1 = mx - mn;
+    m.buckets = B;
+    m.full64 = (m.range_m1 == ~0ull);
+    // R as a double: exact for R <= 2^53, correctly rounded above
+    const double R = m.full64 ? 18446744073709551616.0 : (double)m.range_m1 + 1.0;
+    m.scale = (double)B / R;
+    return m;
+}
+
+// b(k) for 32-bit keys: the numerator is below 2^52, so it and R are exact
+// doubles and a 64-bit remainder check fixes the estimate.  For a key inside
+// [min, max] at most one correction step is taken; the steps are bounded and
+// the result clamped so that a key outside the range cannot index past B.
+__device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint32_t k)
+{
+    const uint64_t x = (uint64_t)(k - (uint32_t)m.mn);
+    const uint64_t num = x * (uint64_t)m.buckets;
+    const uint64_t R = m.range_m1 + 1;   // <= 2^32 for 32-bit keys
+    int64_t q = (int64_t)((double)num * (1.0 / (double)R));
+    if (q >= (int64_t)m.buckets) q = (int64_t)m.buckets - 1;
+    // num - q*R must lie in [0, R)
+    int64_t rem = (int64_t)num - q * (int64_t)R;
+    for (int it = 0; it < 2 && rem < 0; it++) { q--; rem += (int64_t)R; }
+    for (int it = 0; it < 2 && rem >= (int64_t)R; it++) { q++; rem -= (int64_t)R; }
+    if (q < 0) q = 0;
+    if (q >= (int64_t)m.buckets) q = (int64_t)m.buckets - 1;
+    return (uint32_t)q;
+}
+
+// b(k) for 64-bit keys: 128-bit products decide the exact floor
+__device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint64_t k)
+{
+    const uint64_t x = k - m.mn;
+    const uint64_t B = m.buckets;
+    if (m.full64) return (uint32_t)__umul64hi(x, B);   // x * B / 2^64
+    const uint64_t R = m.range_m1 + 1;
+    // P = x * B as (phi, plo)
+    const uint64_t plo = x * B, phi = __umul64hi(x, B);
+    uint64_t q = (uint64_t)((double)x * m.scale);
+    if (q >= B) q = B - 1;
+    // decrease while q * R > P, increase while (q + 1) * R <= P
+    for (int it = 0; it < 4; it++) {
+        const uint64_t lo = q * R, hi = __umul64hi(q, R);
+        if (hi > phi || (hi == phi && lo > plo)) {
+            if (q == 0) break;
+            q--;
+            continue;
+        }
+        const uint64_t lo2 = lo + R, hi2 = hi + (lo2 < lo ? 1u : 0u);
+        if (hi2 < phi || (hi2 == phi && lo2 <= plo)) { q++; continue; }
+        break;
+    }
+    return (uint32_t)(q < B ? q : B - 1);
+}
+
+}  // namespace intsort

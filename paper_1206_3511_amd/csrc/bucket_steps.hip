@@ -1,0 +1,154 @@
+// bucket_steps.hip -- the first two steps of bucket sort (section 2.3,
+// Algorithm 2) as stand-alone kernels: the value range of the keys (min and
+// max, which replace the paper's assumed bound M), and the histogram of the
+// exact bucket index b(k) = floor((k - min) * B / (max - min + 1)).
+
+#include <stdint.h>
+
+#include "bucket_map.hpp"
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace intsort {
+
+constexpr int MM_THREADS = 256;
+
+__global__ void k_minmax_init(uint64_t *minmax)
+{
+    minmax[0] = ~0ull;
+    minmax[1] = 0;
+}
+
+// min and max over all keys: per-thread, per-wave, per-workgroup, then one
+// pair of device-wide atomics per workgroup
+template <typename K>
+__global__ __launch_bounds__(MM_THREADS) void k_minmax(const K *__restrict__ keys, uint64_t n,
+                                                       uint64_t *__restrict__ minmax)
+{
+    constexpr int KPV = 16 / (int)sizeof(K);
+    struct alignas(16) Vec { K v[KPV]; };
+    __shared__ uint64_t s_min[MM_THREADS / WAVE], s_max[MM_THREADS / WAVE];
+    K lo = ~K(0), hi = 0;
+    const uint64_t nvec = n / KPV;
+    const uint64_t stride = (uint64_t)gridDim.x * MM_THREADS;
+    const Vec *vk = reinterpret_cast<const Vec *>(keys);
+    for (uint64_t v = (uint64_t)blockIdx.x * MM_THREADS + threadIdx.x; v < nvec; v += stride) {
+        Vec x = vk[v];
+#pragma unroll
+        for (int e = 0; e < KPV; e++) {
+            lo = x.v[e] < lo ? x.v[e] : lo;
+            hi = x.v[e] > hi ? x.v[e] : hi;
+        }
+    }
+    for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * MM_THREADS + threadIdx.x; i < n; i += stride) {
+        lo = keys[i] < lo ? keys[i] : lo;
+        hi = keys[i] > hi ? keys[i] : hi;
+    }
+    uint64_t l = lo, h = hi;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        uint64_t l2 = __shfl_xor(l, off, WAVE), h2 = __shfl_xor(h, off, WAVE);
+        l = l2 < l ? l2 : l;
+        h = h2 > h ? h2 : h;
+    }
+    const uint32_t wave = threadIdx.x / WAVE;
+    if (lane_id() == 0) { s_min[wave] = l; s_max[wave] = h; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < MM_THREADS / WAVE; w++) {
+            l = s_min[w] < l ? s_min[w] : l;
+            h = s_max[w] > h ? s_max[w] : h;
+        }
+        // 32-bit keys keep their all-ones "no key seen" value out of the max
+        atomicMin(reinterpret_cast<unsigned long long *>(&minmax[0]), (unsigned long long)l);
+        atomicMax(reinterpret_cast<unsigned long long *>(&minmax[1]), (unsigned long long)h);
+    }
+}
+
+hipError_t minmax_run(int key_bytes, const void *keys, uint64_t n, uint64_t *minmax, hipStream_t s)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    uint64_t blocks = (n / (16 / key_bytes) + MM_THREADS - 1) / MM_THREADS;
+    const uint64_t cap = (uint64_t)device_cu_count(dev) * 4;
+    if (blocks > cap) blocks = cap;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(1), 0, s, minmax);
+    if (key_bytes == 4)
+        hipLaunchKernelGGL(k_minmax<uint32_t>, dim3((uint32_t)blocks), dim3(MM_THREADS), 0, s,
+                           static_cast<const uint32_t *>(keys), n, minmax);
+    else
+        hipLaunchKernelGGL(k_minmax<uint64_t>, dim3((uint32_t)blocks), dim3(MM_THREADS), 0, s,
+                           static_cast<const uint64_t *>(keys), n, minmax);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- bucket histogram
+
+constexpr int BH_THREADS = 512;
+constexpr uint32_t BH_LDS_BUCKETS = 16384;   // 64 KB of LDS counters
+
+__global__ void k_zero_u32(uint32_t *p, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+template <typename K, bool LDS>
+__global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__restrict__ keys, uint64_t n,
+                                                                 const uint64_t *__restrict__ minmax,
+                                                                 uint32_t B, uint32_t *__restrict__ counts)
+{
+    __shared__ uint32_t s_c[LDS ? BH_LDS_BUCKETS : 1];
+    const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
+    if (LDS) {
+        for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) s_c[i] = 0;
+        __syncthreads();
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * BH_THREADS;
+    for (uint64_t i = (uint64_t)blockIdx.x * BH_THREADS + threadIdx.x; i < n; i += stride) {
+        const uint32_t b = bucket_of(m, keys[i]);
+        if (LDS) {
+            const uint32_t b0 = first_lane_value(b);
+            const uint64_t act = ballot(true);
+            if (ballot(b != b0) == 0) {
+                if (mbcnt(act) == 0) atomicAdd(&s_c[b0], popc64(act));
+            } else {
+                atomicAdd(&s_c[b], 1u);
+            }
+        } else {
+            atomicAdd(&counts[b], 1u);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) {
+            const uint32_t c = s_c[i];
+            if (c) atomicAdd(&counts[i], c);
+        }
+    }
+}
+
+hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, const uint64_t *minmax,
+                                uint32_t B, uint32_t *counts, hipStream_t s)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipLaunchKernelGGL(k_zero_u32, dim3((B + 255) / 256), dim3(256), 0, s, counts, B);
+    uint64_t blocks = (n + BH_THREADS - 1) / BH_THREADS;
+    const uint64_t cap = (uint64_t)device_cu_count(dev) * 2;
+    if (blocks > cap) blocks = cap;
+    if (blocks == 0) blocks = 1;
+    const bool lds = B <= BH_LDS_BUCKETS;
+    if (key_bytes == 4) {
+        auto kp = static_cast<const uint32_t *>(keys);
+        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint32_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts);
+        else hipLaunchKernelGGL((k_bucket_histogram<uint32_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts);
+    } else {
+        auto kp = static_cast<const uint64_t *>(keys);
+        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint64_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts);
+        else hipLaunchKernelGGL((k_bucket_histogram<uint64_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace intsort

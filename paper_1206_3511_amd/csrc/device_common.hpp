@@ -1,0 +1,87 @@
+// device_common.hpp -- wave64 and workgroup primitives shared by the gfx950
+// kernels of the sort library (no sorting arithmetic lives here).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace intsort {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// number of set bits of `mask` in lanes below the calling lane
+__device__ __forceinline__ uint32_t mbcnt(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t first_lane_value(uint32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// compiler-level ordering point for LDS traffic of one wave (LDS operations
+// of a wave execute in issue order in hardware)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- device-wide (agent scope) relaxed atomics on status words; every XCD
+// sees them, whatever L2 the writer sits behind
+__device__ __forceinline__ uint32_t load_agent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// inclusive scan across the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, WAVE);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over a workgroup of NT threads.
+// s_tmp needs NT/64 + 1 words.  Returns the exclusive prefix; *total gets the
+// sum of all values.  Contains barriers: every thread must call it.
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp, uint32_t *total)
+{
+    constexpr int NW = NT / WAVE;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / WAVE;
+    uint32_t incl = wave_inclusive_scan(v);
+    if (lane == WAVE - 1) s_tmp[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+        uint32_t t = (lane < (uint32_t)NW) ? s_tmp[lane] : 0u;
+        uint32_t ti = wave_inclusive_scan(t);
+        if (lane < (uint32_t)NW) s_tmp[lane] = ti - t;
+        if (lane == (uint32_t)NW - 1) s_tmp[NW] = ti;
+    }
+    __syncthreads();
+    uint32_t res = incl - v + s_tmp[wave];
+    *total = s_tmp[NW];
+    __syncthreads();
+    return res;
+}
+
+}  // namespace intsort

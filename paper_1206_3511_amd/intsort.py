@@ -1,0 +1,316 @@
+"""Python binding of libintsort.so (include/intsort.h).
+
+Argument marshalling only: every step of every sort runs in the HIP kernels of
+the library.  torch supplies device memory (inputs, outputs, workspaces) and
+streams.  If the library is not built the calls raise; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libintsort.so")
+
+# status codes (intsort_status)
+OK = 0
+ERR_INVALID_ARGUMENT = 1
+ERR_MISALIGNED = 2
+ERR_WORKSPACE_TOO_SMALL = 3
+ERR_UNSUPPORTED = 4
+ERR_OVER_BUDGET = 5
+ERR_HIP = 6
+ERR_INTERNAL = 7
+ERR_NOT_READY = 8
+
+U32, U64 = 0, 1
+RADIX, BUCKET = 0, 1
+FLAG_NO_PASS_SKIP = 0x1
+
+EXPORTED = (
+    "intsort_status_string", "intsort_default_options", "intsort_create", "intsort_destroy",
+    "intsort_workspace_size", "intsort_sort_keys", "intsort_sort_pairs",
+    "intsort_segmented_sort_keys", "intsort_segmented_sort_pairs", "intsort_digit_histogram",
+    "intsort_minmax", "intsort_bucket_histogram", "intsort_read_device_error",
+    "intsort_timing_enable", "intsort_timing_read",
+)
+
+KERNEL_KINDS = ("init", "digit_histogram", "pass", "copy", "minmax", "bucket_histogram",
+                "bucket_scatter", "segment_sort", "plan")
+
+
+class IntsortError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("index", ctypes.c_uint32), ("ms", ctypes.c_float)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("algo", ctypes.c_uint32),
+                ("digit_bits", ctypes.c_uint32), ("num_buckets", ctypes.c_uint32),
+                ("lds_cutoff", ctypes.c_uint32), ("max_passes", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+_lock = threading.Lock()
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_i = ctypes.c_int
+_st = ctypes.c_int
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.intsort_status_string.argtypes = [_st]
+        L.intsort_status_string.restype = ctypes.c_char_p
+        L.intsort_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.intsort_default_options.restype = None
+        L.intsort_create.argtypes = [ctypes.POINTER(_vp), _i]
+        L.intsort_destroy.argtypes = [_vp]
+        L.intsort_workspace_size.argtypes = [_vp, _i, _i, _u64, _u64, ctypes.POINTER(Options),
+                                             ctypes.POINTER(ctypes.c_size_t)]
+        L.intsort_sort_keys.argtypes = [_vp, _i, _vp, _vp, _u64, ctypes.POINTER(Options), _vp,
+                                        ctypes.c_size_t, _vp]
+        L.intsort_sort_pairs.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, _u64, ctypes.POINTER(Options),
+                                         _vp, ctypes.c_size_t, _vp]
+        L.intsort_segmented_sort_keys.argtypes = [_vp, _i, _vp, _vp, _u64, _u64, _vp,
+                                                  ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp]
+        L.intsort_segmented_sort_pairs.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, _u64, _u64, _vp,
+                                                   ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp]
+        L.intsort_digit_histogram.argtypes = [_vp, _i, _vp, _u64, ctypes.c_uint32, _vp, _vp,
+                                              ctypes.c_size_t, _vp]
+        L.intsort_minmax.argtypes = [_vp, _i, _vp, _u64, _vp, _vp]
+        L.intsort_bucket_histogram.argtypes = [_vp, _i, _vp, _u64, _vp, ctypes.c_uint32, _vp, _vp]
+        L.intsort_read_device_error.argtypes = [_vp, _vp, ctypes.c_size_t,
+                                                ctypes.POINTER(ctypes.c_uint32), _vp]
+        L.intsort_timing_enable.argtypes = [_vp, _i]
+        L.intsort_timing_read.argtypes = [_vp, ctypes.POINTER(KernelTime), ctypes.c_uint32,
+                                          ctypes.POINTER(ctypes.c_uint32)]
+        for name in EXPORTED:
+            if name not in ("intsort_status_string", "intsort_default_options"):
+                getattr(L, name).restype = _st
+        _lib = L
+        return L
+
+
+def status_string(s: int) -> str:
+    return lib().intsort_status_string(s).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise IntsortError(rc, where)
+
+
+def make_options(algo: str | int = "radix", digit_bits: int = 0, num_buckets: int = 0,
+                 lds_cutoff: int = 0, max_passes: int = 0, skip_passes: bool = True) -> Options:
+    o = Options()
+    lib().intsort_default_options(ctypes.byref(o))
+    o.algo = algo if isinstance(algo, int) else {"radix": RADIX, "bucket": BUCKET}[algo]
+    o.digit_bits = digit_bits
+    o.num_buckets = num_buckets
+    o.lds_cutoff = lds_cutoff
+    o.max_passes = max_passes
+    o.flags = 0 if skip_passes else FLAG_NO_PASS_SKIP
+    return o
+
+
+class Context:
+    """One intsort context per device (device -1: planning only) and a cached
+    workspace tensor per context."""
+
+    def __init__(self, device: int):
+        self.device = device
+        self.handle = _vp()
+        _check(lib().intsort_create(ctypes.byref(self.handle), device), "intsort_create")
+        self._ws = None
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().intsort_destroy(self.handle)
+        except Exception:
+            pass
+
+    def workspace_size(self, kt: int, has_values: bool, n: int, num_segments: int, opts: Options) -> int:
+        out = ctypes.c_size_t(0)
+        _check(lib().intsort_workspace_size(self.handle, kt, int(has_values), n, num_segments,
+                                            ctypes.byref(opts), ctypes.byref(out)), "intsort_workspace_size")
+        return out.value
+
+    def timing(self, enable: bool = True):
+        _check(lib().intsort_timing_enable(self.handle, int(enable)), "intsort_timing_enable")
+
+    def kernel_times(self) -> list[tuple[str, int, float]]:
+        """(kind, index, ms) of every kernel launched since the last read."""
+        buf = (KernelTime * 1024)()
+        cnt = ctypes.c_uint32(0)
+        _check(lib().intsort_timing_read(self.handle, buf, 1024, ctypes.byref(cnt)), "intsort_timing_read")
+        return [(KERNEL_KINDS[buf[i].kind], buf[i].index, buf[i].ms) for i in range(cnt.value)]
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int) -> Context:
+    c = _contexts.get(device)
+    if c is None:
+        c = _contexts[device] = Context(device)
+    return c
+
+
+def _key_type(t: torch.Tensor) -> int:
+    if t.dtype in (torch.uint32, torch.int32):
+        return U32
+    if t.dtype in (torch.uint64, torch.int64):
+        return U64
+    raise TypeError(f"keys must be a 32- or 64-bit integer tensor, got {t.dtype}")
+
+
+def _dev_tensor(t: torch.Tensor, what: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t
+
+
+def _stream_ptr(stream) -> int | None:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def sort(keys: torch.Tensor, algo: str = "radix", out: torch.Tensor | None = None, stream=None,
+         **opt) -> torch.Tensor:
+    """Nondecreasing permutation of `keys` (uint32/int32 or uint64/int64 bit
+    patterns, sorted as unsigned)."""
+    _dev_tensor(keys, "keys")
+    kt = _key_type(keys)
+    out = torch.empty_like(keys) if out is None else _dev_tensor(out, "out")
+    ctx = context(keys.device.index)
+    o = make_options(algo, **opt)
+    n = keys.numel()
+    nb = ctx.workspace_size(kt, False, n, 0, o)
+    ws = ctx.workspace(nb)
+    _check(lib().intsort_sort_keys(ctx.handle, kt, _ptr(keys), _ptr(out), n, ctypes.byref(o), ws.data_ptr(),
+                                   ws.numel(), _stream_ptr(stream)), "intsort_sort_keys")
+    return out
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, algo: str = "radix", out_keys=None, out_vals=None,
+               stream=None, **opt):
+    """Stable key-value sort: equal keys keep their input order."""
+    _dev_tensor(keys, "keys")
+    _dev_tensor(vals, "vals")
+    if vals.dtype not in (torch.uint32, torch.int32) or vals.numel() != keys.numel():
+        raise ValueError("vals must hold one 32-bit value per key")
+    kt = _key_type(keys)
+    ok = torch.empty_like(keys) if out_keys is None else out_keys
+    ov = torch.empty_like(vals) if out_vals is None else out_vals
+    ctx = context(keys.device.index)
+    o = make_options(algo, **opt)
+    n = keys.numel()
+    ws = ctx.workspace(ctx.workspace_size(kt, True, n, 0, o))
+    _check(lib().intsort_sort_pairs(ctx.handle, kt, _ptr(keys), _ptr(ok), _ptr(vals), _ptr(ov), n,
+                                    ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+           "intsort_sort_pairs")
+    return ok, ov
+
+
+def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Tensor | None = None,
+                   algo: str = "radix", out_keys=None, out_vals=None, stream=None, **opt):
+    """Sort every segment [offsets[s], offsets[s+1]) of `keys` on its own.
+    `offsets` is a device uint64/int64 tensor of num_segments + 1 entries."""
+    _dev_tensor(keys, "keys")
+    _dev_tensor(offsets, "offsets")
+    if offsets.dtype not in (torch.uint64, torch.int64):
+        raise TypeError("offsets must be 64-bit")
+    kt = _key_type(keys)
+    S = offsets.numel() - 1
+    ok = torch.empty_like(keys) if out_keys is None else out_keys
+    ctx = context(keys.device.index)
+    o = make_options(algo, **opt)
+    n = keys.numel()
+    ws = ctx.workspace(ctx.workspace_size(kt, vals is not None, n, max(S, 1), o))
+    if vals is None:
+        _check(lib().intsort_segmented_sort_keys(ctx.handle, kt, _ptr(keys), _ptr(ok), n, S, _ptr(offsets),
+                                                 ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                                                 _stream_ptr(stream)), "intsort_segmented_sort_keys")
+        return ok
+    ov = torch.empty_like(vals) if out_vals is None else out_vals
+    _check(lib().intsort_segmented_sort_pairs(ctx.handle, kt, _ptr(keys), _ptr(ok), _ptr(vals), _ptr(ov), n, S,
+                                              _ptr(offsets), ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                                              _stream_ptr(stream)), "intsort_segmented_sort_pairs")
+    return ok, ov
+
+
+def digit_histogram(keys: torch.Tensor, digit_bits: int = 8, stream=None) -> torch.Tensor:
+    """counts[p, v]: keys whose digit p equals v, for every pass p."""
+    _dev_tensor(keys, "keys")
+    kt = _key_type(keys)
+    passes = -(-8 * keys.element_size() // digit_bits)
+    counts = torch.empty(passes * (1 << digit_bits), dtype=torch.uint32, device=keys.device)
+    ctx = context(keys.device.index)
+    o = make_options("radix", digit_bits=digit_bits)
+    ws = ctx.workspace(ctx.workspace_size(kt, False, 0, 0, o))
+    _check(lib().intsort_digit_histogram(ctx.handle, kt, _ptr(keys), keys.numel(), digit_bits, _ptr(counts),
+                                         ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+           "intsort_digit_histogram")
+    return counts.view(passes, 1 << digit_bits)
+
+
+def minmax(keys: torch.Tensor, stream=None) -> torch.Tensor:
+    _dev_tensor(keys, "keys")
+    mm = torch.empty(2, dtype=torch.uint64, device=keys.device)
+    ctx = context(keys.device.index)
+    _check(lib().intsort_minmax(ctx.handle, _key_type(keys), _ptr(keys), keys.numel(), _ptr(mm),
+                                _stream_ptr(stream)), "intsort_minmax")
+    return mm
+
+
+def bucket_histogram(keys: torch.Tensor, mm: torch.Tensor, num_buckets: int, stream=None) -> torch.Tensor:
+    _dev_tensor(keys, "keys")
+    counts = torch.empty(num_buckets, dtype=torch.uint32, device=keys.device)
+    ctx = context(keys.device.index)
+    _check(lib().intsort_bucket_histogram(ctx.handle, _key_type(keys), _ptr(keys), keys.numel(), _ptr(mm),
+                                          num_buckets, _ptr(counts), _stream_ptr(stream)),
+           "intsort_bucket_histogram")
+    return counts
+
+
+def device_error(device: int = 0, stream=None) -> int:
+    """Error word left by the last sort that used this device's cached workspace."""
+    ctx = context(device)
+    if ctx._ws is None:
+        return 0
+    w = ctypes.c_uint32(0)
+    _check(lib().intsort_read_device_error(ctx.handle, ctx._ws.data_ptr(), ctx._ws.numel(), ctypes.byref(w),
+                                           _stream_ptr(stream)), "intsort_read_device_error")
+    return w.value

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/intsort.h declares, validates arguments before it
+touches a device, and sizes workspaces consistently."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1206_3511_amd import intsort as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "intsort.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(intsort_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_what_the_binding_uses():
+    decl = declared_functions()
+    assert set(I.EXPORTED) <= set(decl)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(I.LIB_PATH)
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    for s in range(0, 9):
+        assert I.status_string(s) and I.status_string(s) != "unknown status"
+    assert I.status_string(99) == "unknown status"
+
+
+@pytest.fixture(scope="module")
+def plan_ctx():
+    return I.Context(-1)
+
+
+def _call_sort(ctx, kt=I.U32, kin=0x1000, kout=0x100000, n=100, opts=None, ws=0x1000000, wsb=1 << 30):
+    o = opts if opts is not None else I.make_options()
+    return I.lib().intsort_sort_keys(ctx.handle, kt, kin, kout, n, ctypes.byref(o), ws, wsb, None)
+
+
+def test_validation_order_on_planning_context(plan_ctx):
+    # arguments that pass every check reach the device step, which a
+    # planning context refuses
+    assert _call_sort(plan_ctx) == I.ERR_UNSUPPORTED
+    assert _call_sort(plan_ctx, n=0) == I.OK
+    assert _call_sort(plan_ctx, kt=7) == I.ERR_INVALID_ARGUMENT
+    assert _call_sort(plan_ctx, kin=None) == I.ERR_INVALID_ARGUMENT
+    assert _call_sort(plan_ctx, kout=0x100004) == I.ERR_MISALIGNED
+    # partial overlap of input and output
+    assert _call_sort(plan_ctx, kin=0x1000, kout=0x1010, n=100) == I.ERR_INVALID_ARGUMENT
+    # in place is allowed
+    assert _call_sort(plan_ctx, kin=0x1000, kout=0x1000) == I.ERR_UNSUPPORTED
+    assert _call_sort(plan_ctx, ws=None) == I.ERR_INVALID_ARGUMENT
+    assert _call_sort(plan_ctx, ws=0x1000010) == I.ERR_MISALIGNED
+    assert _call_sort(plan_ctx, wsb=16) == I.ERR_WORKSPACE_TOO_SMALL
+    bad = I.make_options(digit_bits=5)
+    assert _call_sort(plan_ctx, opts=bad) == I.ERR_UNSUPPORTED
+    bad = I.make_options()
+    bad.struct_size = 4
+    assert _call_sort(plan_ctx, opts=bad) == I.ERR_INVALID_ARGUMENT
+    bad = I.make_options()
+    bad.flags = 0x80
+    assert _call_sort(plan_ctx, opts=bad) == I.ERR_INVALID_ARGUMENT
+    # more keys than a 30-bit status word can count
+    assert _call_sort(plan_ctx, kout=1 << 40, n=1 << 31, wsb=1 << 62) == I.ERR_UNSUPPORTED
+
+
+def test_pairs_validation(plan_ctx):
+    o = I.make_options()
+    L = I.lib()
+    n = 64
+    ok = L.intsort_sort_pairs(plan_ctx.handle, I.U32, 0x1000, 0x2000, 0x3000, 0x4000, n, ctypes.byref(o),
+                              0x100000, 1 << 30, None)
+    assert ok == I.ERR_UNSUPPORTED
+    # values overlapping keys
+    assert L.intsort_sort_pairs(plan_ctx.handle, I.U32, 0x1000, 0x2000, 0x1040, 0x4000, n, ctypes.byref(o),
+                                0x100000, 1 << 30, None) == I.ERR_INVALID_ARGUMENT
+    assert L.intsort_sort_pairs(plan_ctx.handle, I.U32, 0x1000, 0x2000, None, 0x4000, n, ctypes.byref(o),
+                                0x100000, 1 << 30, None) == I.ERR_INVALID_ARGUMENT
+
+
+def test_create_rejects_bad_device():
+    h = ctypes.c_void_p()
+    assert I.lib().intsort_create(ctypes.byref(h), -2) == I.ERR_INVALID_ARGUMENT
+    assert I.lib().intsort_create(None, 0) == I.ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("kt", [I.U32, I.U64])
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("bits", [4, 8, 11])
+def test_workspace_monotone(plan_ctx, kt, pairs, bits):
+    o = I.make_options(digit_bits=bits)
+    prev = 0
+    for n in [0, 1, 100, 4095, 4096, 4097, 10**5, 10**6, 10**8]:
+        b = plan_ctx.workspace_size(kt, pairs, n, 0, o)
+        assert b >= prev and b % 256 == 0
+        prev = b
+    # at least the scratch copy of keys (and values)
+    w = 8 if kt == I.U64 else 4
+    assert prev >= 10**8 * (w + (4 if pairs else 0))
