@@ -45,7 +45,9 @@ __device__ __forceinline__ uint32_t digit_at(K k, uint32_t shift, uint32_t mask)
 template <typename K, int BITS>
 struct PassCfg {
     static constexpr int WAVES = (BITS > 8) ? 4 : 8;
-    static constexpr int IPT = sizeof(K) == 4 ? 16 : 8;   // keys per thread
+    // keys per thread: large tiles keep the number of tiles, and with it the
+    // look-back traffic between them, small
+    static constexpr int IPT = sizeof(K) == 4 ? (BITS > 8 ? 16 : 32) : 16;
     static constexpr int NT = WAVES * WAVE;
     static constexpr int TILE = NT * IPT;
     static constexpr int RADIX = 1 << BITS;
@@ -53,15 +55,32 @@ struct PassCfg {
 };
 
 constexpr int HIST_THREADS = 256;
+#ifndef HIST_UNROLL
+#define HIST_UNROLL 4
+#endif
+#ifndef HIST_BLOCKS_PER_CU
+#define HIST_BLOCKS_PER_CU 4
+#endif
+#ifndef HIST_COPIES
+#define HIST_COPIES 4
+#endif
 constexpr uint32_t LOOKBACK_SPIN_LIMIT = 1u << 20;
+#ifndef LOOKBACK_WINDOW
+#define LOOKBACK_WINDOW 4
+#endif
+#ifndef LOOKBACK_SPAN
+#define LOOKBACK_SPAN 32
+#endif
 
 // ------------------------------------------------------------------ init
 
 __global__ __launch_bounds__(256) void k_init(uint32_t *__restrict__ counters,
                                               uint32_t *__restrict__ hist, uint32_t hist_words)
 {
-    for (uint32_t i = threadIdx.x; i < (uint32_t)CTR_WORDS; i += blockDim.x) counters[i] = 0;
-    for (uint32_t i = threadIdx.x; i < hist_words; i += blockDim.x) hist[i] = 0;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < (uint32_t)CTR_WORDS; i += blockDim.x) counters[i] = 0;
+    for (uint32_t i = g; i < hist_words; i += gridDim.x * blockDim.x) hist[i] = 0;
 }
 
 // ------------------------------------------------------------- histogram
@@ -77,7 +96,8 @@ struct HistArgs {
     uint32_t max_passes;   // passes allowed to run (<= passes)
     uint32_t skip;         // skip passes whose digit is constant
     uint32_t in_place;     // keys_in == keys_out
-    uint32_t finalize;     // 0: only count (step-level entry point)
+    uint32_t finalize;     // 0: only count (step-level entry point), no plan
+    uint32_t copies;       // histogram copies the workgroups spread their adds over
 };
 
 // add one key's digit for pass p to the LDS histogram; a wave whose lanes all
@@ -104,9 +124,6 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
     struct alignas(16) Vec { K v[KPV]; };
 
     __shared__ uint32_t s_h[PASSES * RADIX];
-    __shared__ uint32_t s_scan[HIST_THREADS / WAVE + 1];
-    __shared__ uint32_t s_last;
-    __shared__ uint32_t s_const[MAX_PASSES];
 
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < (uint32_t)(PASSES * RADIX); i += HIST_THREADS) s_h[i] = 0;
@@ -120,13 +137,25 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
     const uint32_t n = a.n;
     const uint32_t nvec = n / KPV;
     const Vec *vk = reinterpret_cast<const Vec *>(keys);
-    for (uint32_t v = blockIdx.x * HIST_THREADS + tid; v < nvec; v += gridDim.x * HIST_THREADS) {
-        Vec x = vk[v];
+    // HIST_UNROLL vector loads in flight per thread before any counting
+    const uint32_t step = gridDim.x * HIST_THREADS * HIST_UNROLL;
+    for (uint32_t v0 = blockIdx.x * HIST_THREADS * HIST_UNROLL + tid; v0 < nvec; v0 += step) {
+        Vec x[HIST_UNROLL];
 #pragma unroll
-        for (int e = 0; e < KPV; e++) {
+        for (int u = 0; u < HIST_UNROLL; u++) {
+            const uint32_t v = v0 + u * HIST_THREADS;
+            if (v < nvec) x[u] = vk[v];
+        }
 #pragma unroll
-            for (int p = 0; p < PASSES; p++)
-                hist_add<RADIX>(s_h + p * RADIX, digit_at<K>(x.v[e], (uint32_t)(p * BITS), MASK));
+        for (int u = 0; u < HIST_UNROLL; u++) {
+            if (v0 + u * HIST_THREADS < nvec) {
+#pragma unroll
+                for (int e = 0; e < KPV; e++) {
+#pragma unroll
+                    for (int p = 0; p < PASSES; p++)
+                        hist_add<RADIX>(s_h + p * RADIX, digit_at<K>(x[u].v[e], (uint32_t)(p * BITS), MASK));
+                }
+            }
         }
     }
     if (blockIdx.x == 0) {
@@ -138,30 +167,42 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
         }
     }
     __syncthreads();
+    // workgroups add into one of a.copies copies of the histogram, so that
+    // fewer of them queue on the same device-wide address
+    uint32_t *hdst = a.hist + (blockIdx.x % a.copies) * (uint32_t)(PASSES * RADIX);
     for (uint32_t i = tid; i < (uint32_t)(PASSES * RADIX); i += HIST_THREADS) {
         uint32_t c = s_h[i];
-        if (c) atomicAdd(&a.hist[i], c);
+        if (c) atomicAdd(&hdst[i], c);
     }
-    if (!a.finalize) return;
+}
 
-    // ---- the last workgroup to finish turns counts into offsets and plans
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(&a.counters[CTR_DONE], 1u) == gridDim.x - 1) ? 1u : 0u;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+// Turns the digit counts into exclusive offsets (where the run of every digit
+// value starts in the output of its pass) and plans the passes: which run,
+// which buffer each reads and writes.  One workgroup; runs after the
+// histogram kernel, so every count is complete and visible.
+template <typename K, int BITS>
+__global__ __launch_bounds__(HIST_THREADS) void k_digit_plan(HistArgs a)
+{
+    constexpr int RADIX = 1 << BITS;
+    constexpr int PASSES = PassCfg<K, BITS>::PASSES;
+    constexpr int DPT = RADIX > HIST_THREADS ? RADIX / HIST_THREADS : 1;
+    __shared__ uint32_t s_scan[HIST_THREADS / WAVE + 1];
+    __shared__ uint32_t s_const[MAX_PASSES];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t n = a.n;
 
     if (tid < (uint32_t)MAX_PASSES) s_const[tid] = 0;
     __syncthreads();
-    constexpr int DPT = RADIX > HIST_THREADS ? RADIX / HIST_THREADS : 1;
     for (int p = 0; p < PASSES; p++) {
         uint32_t c[DPT];
         uint32_t mine = 0;
 #pragma unroll
         for (int i = 0; i < DPT; i++) {
             const uint32_t d = tid * DPT + i;
-            c[i] = d < (uint32_t)RADIX ? load_agent(&a.hist[p * RADIX + d]) : 0u;
+            c[i] = 0;
+            if (d < (uint32_t)RADIX)
+                for (uint32_t cp = 0; cp < a.copies; cp++)
+                    c[i] += a.hist[cp * (uint32_t)(PASSES * RADIX) + p * RADIX + d];
             if (c[i] == n) s_const[p] = 1;
             mine += c[i];
         }
@@ -224,6 +265,96 @@ struct PassArgs {
     uint32_t num_tiles;
 };
 
+// Sum of the counts of digit d in tiles 0 .. tile-1.
+//
+// Every tile publishes, per digit, an aggregate word (its own count) and
+// later an inclusive word (count of all tiles up to and including it); after
+// its inclusive words it also raises a per-tile flag.  The walk first reads
+// the flags of the 64 previous tiles (one load per lane) to find the nearest
+// tile that has finished, then fetches the status words of the whole span to
+// it in one batch.  The flag is only a hint: the status words alone decide,
+// and when the hint is missing, stale or too far away the walk falls back to
+// reading LOOKBACK_WINDOW words per round trip: aggregates are added and the
+// walk goes on, an inclusive word ends it, an unpublished word is polled
+// again (bounded: on timeout an error bit is set).
+template <int RADIX>
+__device__ __forceinline__ uint32_t look_back(const uint32_t *status, const uint32_t *tflag, uint32_t tile,
+                                              uint32_t d, uint32_t *err)
+{
+    constexpr int W = LOOKBACK_WINDOW;
+    constexpr int SPAN = LOOKBACK_SPAN;
+    uint32_t prefix = 0;
+    int64_t t = (int64_t)tile - 1;
+    {
+        const int64_t q = (int64_t)tile - 1 - (int64_t)lane_id();
+        const bool f = q >= 0 && load_agent(&tflag[q]) != 0u;
+        const uint64_t m = ballot(f);
+        if (m != 0) {
+            // lanes read tiles tile-1, tile-2, ...: the lowest set lane is
+            // the nearest finished tile
+            const int span = __builtin_ctzll(m) + 1;   // words tile-1 down to that tile
+            if (span <= SPAN) {
+                uint32_t sw[SPAN];
+#pragma unroll
+                for (int k = 0; k < SPAN; k++)
+                    sw[k] = k < span ? load_agent(&status[(uint64_t)(t - k) * RADIX + d]) : 0u;
+                bool stop = false, done = false;
+                int consumed = 0;
+#pragma unroll
+                for (int k = 0; k < SPAN; k++) {
+                    if (!stop && k < span) {
+                        const uint32_t fl = sw[k] >> FLAG_SHIFT;
+                        if (fl == 0) {
+                            stop = true;
+                        } else {
+                            prefix += sw[k] & COUNT_MASK;
+                            consumed++;
+                            if (fl & 2u) { stop = true; done = true; }
+                        }
+                    }
+                }
+                if (done) return prefix;
+                t -= consumed;
+            }
+        }
+    }
+    uint32_t spins = 0;
+    while (t >= 0) {
+        uint32_t s[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            const int64_t tt = t - w;
+            // below tile 0 reads as an empty inclusive word (tile 0 always
+            // publishes an inclusive word, so a correct walk stops earlier)
+            s[w] = tt >= 0 ? load_agent(&status[(uint64_t)tt * RADIX + d]) : FLAG_INC;
+        }
+        bool stop = false, done = false;
+        int consumed = 0;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            if (!stop) {
+                const uint32_t f = s[w] >> FLAG_SHIFT;
+                if (f == 0) {
+                    stop = true;
+                } else {
+                    prefix += s[w] & COUNT_MASK;
+                    consumed++;
+                    if (f & 2u) { stop = true; done = true; }
+                }
+            }
+        }
+        if (done) return prefix;
+        t -= consumed;
+        if (t < 0) break;
+        if (consumed == 0) {
+            if (++spins > LOOKBACK_SPIN_LIMIT) { atomicOr(err, DEVERR_LOOKBACK_TIMEOUT); return prefix; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    atomicOr(err, DEVERR_BAD_TILE);
+    return prefix;
+}
+
 template <typename K, int BITS, bool PAIRS>
 __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K> a)
 {
@@ -256,6 +387,9 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     }
     uint32_t *status = (ord & 1) ? a.status1 : a.status0;
     uint32_t *status_next = (ord & 1) ? a.status0 : a.status1;
+    // per-tile "inclusive words published" flags follow each status array
+    uint32_t *tflag = status + (uint64_t)a.num_tiles * RADIX;
+    uint32_t *tflag_next = status_next + (uint64_t)a.num_tiles * RADIX;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
@@ -337,8 +471,8 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     }
     __syncthreads();
 
-    // ---- per digit: offsets of every wave inside the tile, the tile count,
-    // its publication, and the look-back over earlier tiles
+    // ---- per digit: offsets of every wave inside the tile and the tile's
+    // count, published at once so that later tiles can look back over it
     uint32_t tcnt[DPT];
     uint32_t mine = 0;
 #pragma unroll
@@ -359,50 +493,44 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         mine += tcnt[i];
     }
     uint32_t total_unused;
-    uint32_t texcl = block_exclusive_scan<NT>(mine, s_scan, &total_unused);
+    uint32_t texcl[DPT];
+    texcl[0] = block_exclusive_scan<NT>(mine, s_scan, &total_unused);
 #pragma unroll
     for (int i = 0; i < DPT; i++) {
         const uint32_t d = tid * DPT + i;
-        if (d < (uint32_t)RADIX) {
-            uint32_t prefix = 0;
-            if (tile > 0) {
-                int64_t t = (int64_t)tile - 1;
-                uint32_t spins = 0;
-                while (true) {
-                    const uint32_t s = load_agent(&status[(uint64_t)t * RADIX + d]);
-                    if ((s >> FLAG_SHIFT) == 0) {
-                        if (++spins > LOOKBACK_SPIN_LIMIT) {
-                            atomicOr(&a.counters[CTR_ERROR], DEVERR_LOOKBACK_TIMEOUT);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
-                    }
-                    prefix += s & COUNT_MASK;
-                    if (s & FLAG_INC) break;
-                    if (--t < 0) {
-                        atomicOr(&a.counters[CTR_ERROR], DEVERR_BAD_TILE);
-                        break;
-                    }
-                }
-                store_agent(&status[(uint64_t)tile * RADIX + d], FLAG_INC | (prefix + tcnt[i]));
-            }
-            s_tile_excl[d] = texcl;
-            s_gbase[d] = a.excl[d] + prefix - texcl;
-            store_agent(&status_next[(uint64_t)tile * RADIX + d], 0u);
-        }
-        texcl += tcnt[i];
+        if (i > 0) texcl[i] = texcl[i - 1] + tcnt[i - 1];
+        if (d < (uint32_t)RADIX) s_tile_excl[d] = texcl[i];
     }
     __syncthreads();
 
-    // ---- reorder the tile through LDS into digit order
+    // ---- reorder the tile through LDS into digit order; this needs only
+    // tile-local offsets, so it runs before the look-back
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
         const uint32_t d = digit_at<K>(k[j], shift, MASK);
         rk[j] += s_tile_excl[d] + s_wcnt[wave * RADIX + d];
         s_stage[rk[j]] = k[j];
     }
+
+    // ---- look-back: the counts of this digit in all earlier tiles
+#pragma unroll
+    for (int i = 0; i < DPT; i++) {
+        const uint32_t d = tid * DPT + i;
+        if (d < (uint32_t)RADIX) {
+            uint32_t prefix = 0;
+            if (tile > 0) {
+                prefix = look_back<RADIX>(status, tflag, tile, d, &a.counters[CTR_ERROR]);
+                store_agent(&status[(uint64_t)tile * RADIX + d], FLAG_INC | (prefix + tcnt[i]));
+            }
+            s_gbase[d] = a.excl[d] + prefix - texcl[i];
+            store_agent(&status_next[(uint64_t)tile * RADIX + d], 0u);
+        }
+    }
     __syncthreads();
+    if (tid == 0) {
+        store_agent(&tflag[tile], 1u);
+        store_agent(&tflag_next[tile], 0u);
+    }
 
     // ---- contiguous runs of each digit go to their global offsets
     uint32_t dest[PAIRS ? IPT : 1];
@@ -486,11 +614,11 @@ RadixLayout radix_layout(int key_bytes, bool pairs, uint64_t n, int bits)
     L.counters = take((size_t)CTR_WORDS * 4);   // always first: fixed error-word offset
     L.tmp_keys = take(n * (size_t)key_bytes);
     L.tmp_vals = take(pairs ? n * 4 : 0);
-    L.hist = take((size_t)L.g.passes * L.g.radix * 4);
+    L.hist = take((size_t)HIST_COPIES * L.g.passes * L.g.radix * 4);
     L.excl = take((size_t)L.g.passes * L.g.radix * 4);
     L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
-    L.status0 = take((size_t)L.num_tiles * L.g.radix * 4);
-    L.status1 = take((size_t)L.num_tiles * L.g.radix * 4);
+    L.status0 = take((size_t)L.num_tiles * (L.g.radix + 1) * 4);
+    L.status1 = take((size_t)L.num_tiles * (L.g.radix + 1) * 4);
     L.total = off;
     return L;
 }
@@ -525,7 +653,9 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
     uint32_t *counters = reinterpret_cast<uint32_t *>(ws + L.counters);
     Timer *t = c.timer;
     if (t) t->start(s);
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, counters, hist, (uint32_t)(C::PASSES * C::RADIX));
+    const uint32_t copies = finalize ? (uint32_t)HIST_COPIES : 1u;
+    const uint32_t hist_words = copies * (uint32_t)(C::PASSES * C::RADIX);
+    hipLaunchKernelGGL(k_init, dim3((hist_words + 255) / 256), dim3(256), 0, s, counters, hist, hist_words);
     if (t) t->mark(INTSORT_KERNEL_INIT, 0, s);
     HistArgs h{};
     h.hist = hist;
@@ -533,20 +663,25 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
     h.plan = reinterpret_cast<uint32_t *>(ws + L.plan);
     h.counters = counters;
     h.status0 = finalize ? reinterpret_cast<uint32_t *>(ws + L.status0) : nullptr;
-    h.status0_words = finalize ? L.num_tiles * (uint64_t)C::RADIX : 0;
+    h.status0_words = finalize ? L.num_tiles * (uint64_t)(C::RADIX + 1) : 0;
     h.n = (uint32_t)c.n;
     h.max_passes = (uint32_t)c.max_passes;
     h.skip = c.skip_constant_digits ? 1u : 0u;
     h.in_place = c.keys_in == c.keys_out ? 1u : 0u;
     h.finalize = finalize ? 1u : 0u;
+    h.copies = copies;
     const uint64_t nvec = c.n / (16 / sizeof(K));
-    uint64_t blocks = (nvec + HIST_THREADS - 1) / HIST_THREADS;
-    const uint64_t cap = (uint64_t)current_cus() * 4;
+    uint64_t blocks = (nvec + HIST_THREADS * HIST_UNROLL - 1) / (HIST_THREADS * HIST_UNROLL);
+    const uint64_t cap = (uint64_t)current_cus() * HIST_BLOCKS_PER_CU;
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL((k_digit_histogram<K, BITS>), dim3((uint32_t)blocks), dim3(HIST_THREADS), 0, s,
                        static_cast<const K *>(c.keys_in), h);
     if (t) t->mark(INTSORT_KERNEL_DIGIT_HISTOGRAM, 0, s);
+    if (finalize) {
+        hipLaunchKernelGGL((k_digit_plan<K, BITS>), dim3(1), dim3(HIST_THREADS), 0, s, h);
+        if (t) t->mark(INTSORT_KERNEL_PLAN, 0, s);
+    }
     return hipGetLastError();
 }
 
