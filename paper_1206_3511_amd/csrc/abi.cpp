@@ -145,6 +145,7 @@ intsort_status sort_common(intsort_ctx *ctx, intsort_key_type kt, const void *ke
     b.opts = o;
     b.L = bucket_layout(kb, pairs, n, o);
     b.ws = static_cast<char *>(ws);
+    b.timer = ctx->timer;
     return from_hip(bucket_sort_run(b, s));
 }
 
@@ -346,6 +347,7 @@ static intsort_status segmented_common(intsort_ctx *ctx, intsort_key_type kt, co
     c.opts = o;
     c.L = L;
     c.ws = static_cast<char *>(ws);
+    c.timer = ctx->timer;
     return from_hip(segmented_sort_run(c, static_cast<hipStream_t>(stream)));
 }
 

@@ -85,3 +85,16 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
 }
 
 }  // namespace intsort
+
+namespace intsort {
+
+// fills p[0..n) with v (grid-stride); a kernel, so that it can sit in a
+// captured graph where memset nodes are avoided
+template <typename T>
+__global__ void k_fill(T *p, uint64_t n, T v)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+}  // namespace intsort

@@ -31,6 +31,9 @@ constexpr int MAX_PASSES = 16;
 constexpr int CTR_TILE = 0;
 constexpr int CTR_DONE = MAX_PASSES;
 constexpr int CTR_ERROR = MAX_PASSES + 1;
+constexpr int CTR_SEG_CLASS = 32;   // [4] segments per on-chip size class
+constexpr int CTR_SEG_SLOTS = 36;   // large segments
+constexpr int CTR_SEG_TILES = 37;   // tiles of the large segments
 constexpr int CTR_WORDS = 64;
 
 // HIP events around kernels (profiling only).  Events accumulate over calls

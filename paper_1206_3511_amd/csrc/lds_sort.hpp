@@ -1,0 +1,151 @@
+// lds_sort.hpp -- one workgroup sorts one short segment entirely on chip.
+//
+// This is the per-bucket sort of bucket sort (section 2.3, Algorithm 2 sorts
+// every bucket with insertion sort, Algorithm 1) and the small-segment path of
+// the segmented sort.  Any stable sort gives the same bytes; here it is an LSD
+// radix sort over 8-bit digits whose passes never leave LDS: each pass ranks
+// the keys stably (wave_rank plus a scan over digits and waves) and reorders
+// them through LDS.  A digit that is the same for every key of the segment
+// leaves it unchanged, so its pass is skipped.
+#pragma once
+
+#include <stdint.h>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+#include "onesweep.hpp"
+
+namespace intsort {
+
+template <typename K>
+struct LdsSortArgs {
+    const K *in;
+    K *out;
+    const uint32_t *vin;
+    uint32_t *vout;
+    const uint64_t *offsets;     // [segments + 1]
+    const uint32_t *list;        // segment ids of this size class
+    const uint32_t *list_count;  // device count of listed segments
+};
+
+template <typename K, bool PAIRS, int NT, int IPT>
+__global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<K> a)
+{
+    constexpr int WAVES = NT / WAVE;
+    constexpr int TILE = NT * IPT;
+    constexpr int RADIX = 256;
+    constexpr int PASSES = (int)sizeof(K);
+    constexpr int DPT = RADIX > NT ? RADIX / NT : 1;
+    constexpr int STAGE_BYTES = (TILE * (int)sizeof(K) > WAVES * RADIX * 8) ? TILE * (int)sizeof(K)
+                                                                           : WAVES * RADIX * 8;
+    __shared__ alignas(16) unsigned char s_raw[STAGE_BYTES];
+    __shared__ uint32_t s_vstage[PAIRS ? TILE : 1];
+    __shared__ uint32_t s_wcnt[WAVES * RADIX];
+    __shared__ uint32_t s_excl[RADIX];
+    __shared__ uint32_t s_scan[WAVES + 1];
+    __shared__ K s_diff[WAVES];
+    K *s_stage = reinterpret_cast<K *>(s_raw);
+    uint64_t *s_bits = reinterpret_cast<uint64_t *>(s_raw);
+
+    if (blockIdx.x >= *a.list_count) return;
+    const uint32_t seg = a.list[blockIdx.x];
+    const uint64_t start = a.offsets[seg];
+    const uint32_t m = (uint32_t)(a.offsets[seg + 1] - start);   // <= TILE by classification
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    const uint32_t lofs = wave * (IPT * WAVE) + lane;
+
+    K k[IPT];
+    uint32_t v[PAIRS ? IPT : 1];
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        const bool in = lofs + j * WAVE < m;
+        k[j] = in ? a.in[start + lofs + j * WAVE] : ~K(0);
+        if (PAIRS) v[j] = in ? a.vin[start + lofs + j * WAVE] : 0u;
+    }
+
+    // bits in which some key differs from the first one
+    const K ref = m > 0 ? a.in[start] : K(0);
+    K diff = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; j++)
+        if (lofs + j * WAVE < m) diff |= k[j] ^ ref;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) diff |= __shfl_xor(diff, off, WAVE);
+    if (lane == 0) s_diff[wave] = diff;
+    __syncthreads();
+    diff = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; w++) diff |= s_diff[w];
+
+    uint32_t *wcnt = s_wcnt + wave * RADIX;
+    uint64_t *bits = s_bits + wave * RADIX;
+    const uint64_t lanebit = 1ull << lane;
+    for (int p = 0; p < PASSES; p++) {
+        const uint32_t shift = 8u * (uint32_t)p;
+        if (((diff >> shift) & 0xffu) == 0) continue;   // the same for every workgroup thread
+        for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) {
+            s_wcnt[i] = 0;
+            s_bits[i] = 0;
+        }
+        __syncthreads();
+        uint32_t rk[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; j++) {
+            const uint32_t d = lofs + j * WAVE < m ? digit_at<K>(k[j], shift, 0xffu) : 0xffu;
+            rk[j] = wave_rank<8>(d, wcnt, bits, lanebit, lane);
+        }
+        __syncthreads();
+        uint32_t tcnt[DPT];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < DPT; i++) {
+            const uint32_t d = tid * DPT + i;
+            tcnt[i] = 0;
+            if (d < (uint32_t)RADIX) {
+                uint32_t run = 0;
+#pragma unroll
+                for (int w = 0; w < WAVES; w++) {
+                    const uint32_t c = s_wcnt[w * RADIX + d];
+                    s_wcnt[w * RADIX + d] = run;
+                    run += c;
+                }
+                tcnt[i] = run;
+            }
+            mine += tcnt[i];
+        }
+        uint32_t total_unused;
+        uint32_t ex = block_exclusive_scan<NT>(mine, s_scan, &total_unused);
+#pragma unroll
+        for (int i = 0; i < DPT; i++) {
+            const uint32_t d = tid * DPT + i;
+            if (d < (uint32_t)RADIX) s_excl[d] = ex;
+            ex += tcnt[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; j++) {
+            const uint32_t d = lofs + j * WAVE < m ? digit_at<K>(k[j], shift, 0xffu) : 0xffu;
+            const uint32_t pos = s_excl[d] + s_wcnt[wave * RADIX + d] + rk[j];
+            s_stage[pos] = k[j];
+            if (PAIRS) s_vstage[pos] = v[j];
+        }
+        __syncthreads();
+        // padding keys took the largest digit and the last positions, so
+        // the first m positions hold the segment in its new order
+#pragma unroll
+        for (int j = 0; j < IPT; j++) {
+            k[j] = s_stage[lofs + j * WAVE];
+            if (PAIRS) v[j] = s_vstage[lofs + j * WAVE];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        if (lofs + j * WAVE < m) {
+            a.out[start + lofs + j * WAVE] = k[j];
+            if (PAIRS) a.vout[start + lofs + j * WAVE] = v[j];
+        }
+    }
+}
+
+}  // namespace intsort

@@ -1,0 +1,489 @@
+// onesweep.hpp -- one stable counting-sort pass over tiles of keys, shared by
+// the radix sort, the bucket scatter of bucket sort and the large segments of
+// the segmented sort.
+//
+// A pass places every key at (start of its digit's run) + (number of keys
+// with the same digit before it): the placement loop of COUNTING-SORT
+// (section 2.4, Algorithm 3), done for all tiles of the input at once.  Each
+// workgroup takes the next tile, ranks its keys stably in LDS, publishes its
+// per-digit counts, learns the counts of all earlier tiles of its segment by
+// a decoupled look-back over per-(tile, digit) status words, reorders the
+// tile in LDS into digit order and writes every digit's run contiguously.
+//
+// Two policies make the kernel serve several callers:
+//   Digit  maps a key to its digit: an r-bit field of the key (radix sort)
+//          or an 8-bit field of the exact bucket index (bucket sort).
+//   Tiles  maps a tile id to its keys and to the global start of every digit
+//          run: one array cut into equal tiles, or a list of tiles of many
+//          independent segments (a look-back never leaves its segment).
+#pragma once
+
+#include <stdint.h>
+
+#include "bucket_map.hpp"
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace intsort {
+
+// tile shape of the pass kernel for a key type and digit width
+template <typename K, int BITS>
+struct PassCfg {
+    static constexpr int WAVES = (BITS > 8) ? 4 : 8;
+    // keys per thread: large tiles keep the number of tiles, and with it the
+    // look-back traffic between them, small
+    static constexpr int IPT = sizeof(K) == 4 ? (BITS > 8 ? 16 : 32) : 16;
+    static constexpr int NT = WAVES * WAVE;
+    static constexpr int TILE = NT * IPT;
+    static constexpr int RADIX = 1 << BITS;
+    static constexpr int PASSES = (8 * (int)sizeof(K) + BITS - 1) / BITS;
+};
+
+constexpr uint32_t LOOKBACK_SPIN_LIMIT = 1u << 20;
+#ifndef LOOKBACK_WINDOW
+#define LOOKBACK_WINDOW 4
+#endif
+#ifndef LOOKBACK_SPAN
+#define LOOKBACK_SPAN 32
+#endif
+
+// ---------------------------------------------------------------- digits
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_at(K k, uint32_t shift, uint32_t mask)
+{
+    return (uint32_t)(k >> shift) & mask;
+}
+
+// digit p of radix sort: (k >> p*r) & (2^r - 1)
+struct RadixDigit {
+    uint32_t shift, mask;
+    __device__ RadixDigit prepare() const { return *this; }
+    template <typename K>
+    __device__ __forceinline__ uint32_t operator()(K k) const { return digit_at<K>(k, shift, mask); }
+};
+
+// an 8-bit field of the bucket index b(k) of bucket sort; min and max are
+// read from device memory when the kernel starts
+struct BucketDigitArgs {
+    const uint64_t *minmax;
+    uint32_t buckets, shift, mask;
+    struct Fn {
+        BucketMap m;
+        uint32_t shift, mask;
+        template <typename K>
+        __device__ __forceinline__ uint32_t operator()(K k) const { return (bucket_of(m, k) >> shift) & mask; }
+    };
+    __device__ Fn prepare() const { return Fn{make_bucket_map(minmax[0], minmax[1], buckets), shift, mask}; }
+};
+
+// ---------------------------------------------------------------- tiles
+
+struct TileInfo {
+    uint32_t start;       // index of the tile's first key
+    uint32_t count;       // keys in the tile (<= TILE)
+    uint32_t first_tile;  // id of the first tile of the tile's segment
+    uint32_t base;        // index of the segment's first key
+    const uint32_t *excl; // exclusive digit offsets inside the segment
+};
+
+// one array of n keys in tiles of TILE keys
+struct PlainTiles {
+    uint32_t n, num_tiles;
+    const uint32_t *excl;   // [radix] exclusive digit offsets of this pass
+    template <int TILE>
+    __device__ __forceinline__ bool get(uint32_t t, TileInfo &ti) const
+    {
+        if (t >= num_tiles) return false;
+        ti.start = t * (uint32_t)TILE;
+        ti.count = min((uint32_t)TILE, n - ti.start);
+        ti.first_tile = 0;
+        ti.base = 0;
+        ti.excl = excl;
+        return true;
+    }
+    __device__ bool missing_is_error() const { return true; }
+};
+
+// tiles of many segments, listed on the device; the tiles of one segment
+// have consecutive ids
+struct TileDesc {
+    uint32_t slot;        // row of the segment in seg_excl
+    uint32_t first_tile;
+    uint32_t start;
+    uint32_t count;
+    uint32_t base;
+    uint32_t pad[3];
+};
+
+struct SegTiles {
+    const TileDesc *desc;
+    const uint32_t *num_tiles;   // device count of listed tiles
+    const uint32_t *seg_excl;    // [slot][radix] for this pass
+    uint32_t radix;
+    template <int TILE>
+    __device__ __forceinline__ bool get(uint32_t t, TileInfo &ti) const
+    {
+        if (t >= *num_tiles) return false;
+        const TileDesc d = desc[t];
+        ti.start = d.start;
+        ti.count = d.count;
+        ti.first_tile = d.first_tile;
+        ti.base = d.base;
+        ti.excl = seg_excl + (uint64_t)d.slot * radix;
+        return true;
+    }
+    __device__ bool missing_is_error() const { return false; }
+};
+
+// ---------------------------------------------------------------- ranking
+
+// Stable rank of one slot of a wave (64 keys, one per lane, in lane order)
+// among the keys the wave has ranked so far: the keys with the same digit in
+// earlier slots (the per-wave counter wcnt[d]) plus the lanes below with the
+// same digit in this slot.  Peers come from a per-wave LDS bitmap that every
+// lane ORs its bit into; a wave whose lanes all hold one digit skips it.  For
+// digits wider than 8 bits the bitmap is indexed by the low 8 bits and the
+// remaining bits are matched with ballots.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_rank(uint32_t d, uint32_t *wcnt, uint64_t *bits, uint64_t lanebit,
+                                              uint32_t lane)
+{
+    const uint32_t d0 = first_lane_value(d);
+    // the active lanes, taken before any branch: a ballot inside a branch
+    // sees only the lanes that took it
+    const uint64_t act = ballot(true);
+    uint32_t r;
+    if (ballot(d != d0) == 0) {
+        const uint32_t c = wcnt[d0];
+        const uint32_t below = mbcnt(act);
+        r = c + below;
+        wave_sync();
+        if (below == 0) wcnt[d0] = c + popc64(act);
+        wave_sync();
+    } else {
+        const uint32_t h = BITS > 8 ? (d & 255u) : d;
+        atomicOr(reinterpret_cast<unsigned long long *>(&bits[h]), (unsigned long long)lanebit);
+        wave_sync();
+        uint64_t peers = __hip_atomic_load(&bits[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (BITS > 8) {
+#pragma unroll
+            for (int b = 8; b < BITS; b++) {
+                const bool on = (d >> b) & 1u;
+                const uint64_t bb = ballot(on);
+                peers &= on ? bb : ~bb;
+            }
+        }
+        const uint32_t below = mbcnt(peers);
+        const uint32_t c = wcnt[d];
+        r = c + below;
+        wave_sync();
+        if (below == 0) {
+            wcnt[d] = c + popc64(peers);
+            __hip_atomic_store(&bits[h], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+        wave_sync();
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------- look-back
+
+// Sum of the counts of digit d in tiles first_tile .. tile-1 of one segment.
+//
+// Every tile publishes, per digit, an aggregate word (its own count) and
+// later an inclusive word (count of all tiles of its segment up to and
+// including it; the first tile of a segment publishes its inclusive word at
+// once); after its inclusive words it also raises a per-tile flag.  The walk
+// first reads the flags of the 64 previous tiles (one load per lane) to find
+// the nearest finished tile, then fetches the status words of the whole span
+// to it in one batch.  The flag is only a hint: the status words alone
+// decide, and when the hint is missing, stale or too far away the walk falls
+// back to reading LOOKBACK_WINDOW words per round trip: aggregates are added
+// and the walk goes on, an inclusive word ends it, an unpublished word is
+// polled again (bounded: on timeout an error bit is set).
+template <int RADIX>
+__device__ __forceinline__ uint32_t look_back(const uint32_t *status, const uint32_t *tflag, uint32_t tile,
+                                              uint32_t first_tile, uint32_t d, uint32_t *err)
+{
+    constexpr int W = LOOKBACK_WINDOW;
+    constexpr int SPAN = LOOKBACK_SPAN;
+    uint32_t prefix = 0;
+    int64_t t = (int64_t)tile - 1;
+    const int64_t lo = first_tile;
+    {
+        const int64_t q = (int64_t)tile - 1 - (int64_t)lane_id();
+        const bool f = q >= lo && load_agent(&tflag[q]) != 0u;
+        const uint64_t m = ballot(f);
+        if (m != 0) {
+            // lanes read tiles tile-1, tile-2, ...: the lowest set lane is
+            // the nearest finished tile
+            const int span = __builtin_ctzll(m) + 1;
+            if (span <= SPAN) {
+                uint32_t sw[SPAN];
+#pragma unroll
+                for (int k = 0; k < SPAN; k++)
+                    sw[k] = k < span ? load_agent(&status[(uint64_t)(t - k) * RADIX + d]) : 0u;
+                bool stop = false, done = false;
+                int consumed = 0;
+#pragma unroll
+                for (int k = 0; k < SPAN; k++) {
+                    if (!stop && k < span) {
+                        const uint32_t fl = sw[k] >> FLAG_SHIFT;
+                        if (fl == 0) {
+                            stop = true;
+                        } else {
+                            prefix += sw[k] & COUNT_MASK;
+                            consumed++;
+                            if (fl & 2u) { stop = true; done = true; }
+                        }
+                    }
+                }
+                if (done) return prefix;
+                t -= consumed;
+            }
+        }
+    }
+    uint32_t spins = 0;
+    while (t >= lo) {
+        uint32_t s[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            const int64_t tt = t - w;
+            // before the segment's first tile reads as an empty inclusive
+            // word (that tile's own word is inclusive, so a correct walk
+            // stops there)
+            s[w] = tt >= lo ? load_agent(&status[(uint64_t)tt * RADIX + d]) : FLAG_INC;
+        }
+        bool stop = false, done = false;
+        int consumed = 0;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            if (!stop) {
+                const uint32_t f = s[w] >> FLAG_SHIFT;
+                if (f == 0) {
+                    stop = true;
+                } else {
+                    prefix += s[w] & COUNT_MASK;
+                    consumed++;
+                    if (f & 2u) { stop = true; done = true; }
+                }
+            }
+        }
+        if (done) return prefix;
+        t -= consumed;
+        if (consumed == 0) {
+            if (++spins > LOOKBACK_SPIN_LIMIT) { atomicOr(err, DEVERR_LOOKBACK_TIMEOUT); return prefix; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    atomicOr(err, DEVERR_BAD_TILE);
+    return prefix;
+}
+
+// ---------------------------------------------------------------- the pass
+
+template <typename K>
+struct PassArgs {
+    const K *in;
+    K *out;
+    K *tmp;
+    const uint32_t *vin;
+    uint32_t *vout;
+    uint32_t *vtmp;
+    const uint32_t *plan;   // this pass's plan words: active, src, dst, ordinal
+    uint32_t *status0;      // look-back words (+ tile flags) for even / odd active passes
+    uint32_t *status1;
+    uint32_t *counters;
+    uint32_t n;             // keys in the whole buffer (bound of every store)
+    uint32_t pass;
+    uint32_t tile_capacity; // tiles the status arrays hold
+};
+
+template <typename K, int BITS, bool PAIRS, class DigitArgs, class Tiles>
+__global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K> a, DigitArgs da, Tiles tl)
+{
+    using C = PassCfg<K, BITS>;
+    constexpr int RADIX = C::RADIX, NT = C::NT, WAVES = C::WAVES, IPT = C::IPT, TILE = C::TILE;
+    constexpr uint32_t MASK = RADIX - 1;
+    constexpr int BM = BITS > 8 ? 256 : RADIX;          // peer bitmap words per wave
+    constexpr int DPT = RADIX > NT ? RADIX / NT : 1;    // digits per thread in digit phases
+    static_assert(TILE * sizeof(K) >= WAVES * BM * sizeof(uint64_t), "bitmaps alias the stage");
+    static_assert(RADIX <= NT * DPT, "digit phase covers every digit");
+
+    __shared__ alignas(16) unsigned char s_raw[TILE * sizeof(K)];
+    __shared__ uint32_t s_wcnt[WAVES * RADIX];
+    __shared__ uint32_t s_tile_excl[RADIX];
+    __shared__ uint32_t s_gbase[RADIX];
+    __shared__ uint32_t s_scan[NT / WAVE + 1];
+    __shared__ uint32_t s_tile;
+    K *s_stage = reinterpret_cast<K *>(s_raw);
+    uint64_t *s_bits = reinterpret_cast<uint64_t *>(s_raw);
+
+    if (a.plan[0] == 0) return;   // pass skipped: the same for every workgroup
+    const uint32_t srcc = a.plan[1], dstc = a.plan[2], ord = a.plan[3];
+    const K *src = srcc == BUF_IN ? a.in : (srcc == BUF_OUT ? a.out : a.tmp);
+    K *dst = dstc == BUF_OUT ? a.out : a.tmp;
+    const uint32_t *vsrc = nullptr;
+    uint32_t *vdst = nullptr;
+    if (PAIRS) {
+        vsrc = srcc == BUF_IN ? a.vin : (srcc == BUF_OUT ? a.vout : a.vtmp);
+        vdst = dstc == BUF_OUT ? a.vout : a.vtmp;
+    }
+    uint32_t *status = (ord & 1) ? a.status1 : a.status0;
+    uint32_t *status_next = (ord & 1) ? a.status0 : a.status1;
+    // per-tile "inclusive words published" flags follow each status array
+    uint32_t *tflag = status + (uint64_t)a.tile_capacity * RADIX;
+    uint32_t *tflag_next = status_next + (uint64_t)a.tile_capacity * RADIX;
+    const auto dg = da.prepare();
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = tid / WAVE;
+    const uint32_t n = a.n;
+
+    for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
+    for (uint32_t i = tid; i < (uint32_t)(WAVES * BM); i += NT) s_bits[i] = 0;
+    if (tid == 0) s_tile = atomicAdd(&a.counters[CTR_TILE + a.pass], 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    TileInfo ti;
+    if (tile >= a.tile_capacity || !tl.template get<TILE>(tile, ti)) {
+        // past the listed tiles (a grid sized for the most tiles possible),
+        // or counters that were not reset: never index past the arrays
+        if (tid == 0 && (tile >= a.tile_capacity || tl.missing_is_error()))
+            atomicOr(&a.counters[CTR_ERROR], DEVERR_BAD_TILE);
+        return;
+    }
+    const uint32_t valid = ti.count;
+    const bool first = tile == ti.first_tile;
+
+    // ---- load: wave-striped, so (wave, item, lane) order is index order
+    K k[IPT];
+    uint32_t v[PAIRS ? IPT : 1];
+    const uint32_t lofs = wave * (IPT * WAVE) + lane;   // tile-local index of item 0
+    const uint32_t wofs = ti.start + lofs;
+    if (valid == (uint32_t)TILE) {
+#pragma unroll
+        for (int j = 0; j < IPT; j++) {
+            k[j] = src[wofs + j * WAVE];
+            if (PAIRS) v[j] = vsrc[wofs + j * WAVE];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < IPT; j++) {
+            const bool in = lofs + j * WAVE < valid;
+            k[j] = in ? src[wofs + j * WAVE] : ~K(0);
+            if (PAIRS) v[j] = in ? vsrc[wofs + j * WAVE] : 0u;
+        }
+    }
+    // keys past the end of the tile take the largest digit and so rank last
+    auto digit_of = [&](int j) -> uint32_t {
+        return (valid == (uint32_t)TILE || lofs + j * WAVE < valid) ? dg(k[j]) : MASK;
+    };
+
+    // ---- stable rank inside the wave
+    uint32_t rk[IPT];
+    uint32_t *wcnt = s_wcnt + wave * RADIX;
+    uint64_t *bits = s_bits + wave * BM;
+    const uint64_t lanebit = 1ull << lane;
+#pragma unroll
+    for (int j = 0; j < IPT; j++) rk[j] = wave_rank<BITS>(digit_of(j), wcnt, bits, lanebit, lane);
+    __syncthreads();
+
+    // ---- per digit: offsets of every wave inside the tile and the tile's
+    // count, published at once so that later tiles can look back over it
+    uint32_t tcnt[DPT];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; i++) {
+        const uint32_t d = tid * DPT + i;
+        tcnt[i] = 0;
+        if (d < (uint32_t)RADIX) {
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; w++) {
+                const uint32_t c = s_wcnt[w * RADIX + d];
+                s_wcnt[w * RADIX + d] = run;
+                run += c;
+            }
+            tcnt[i] = run;
+            store_agent(&status[(uint64_t)tile * RADIX + d], (first ? FLAG_INC : FLAG_AGG) | run);
+        }
+        mine += tcnt[i];
+    }
+    uint32_t total_unused;
+    uint32_t texcl[DPT];
+    texcl[0] = block_exclusive_scan<NT>(mine, s_scan, &total_unused);
+#pragma unroll
+    for (int i = 0; i < DPT; i++) {
+        const uint32_t d = tid * DPT + i;
+        if (i > 0) texcl[i] = texcl[i - 1] + tcnt[i - 1];
+        if (d < (uint32_t)RADIX) s_tile_excl[d] = texcl[i];
+    }
+    __syncthreads();
+
+    // ---- reorder the tile through LDS into digit order; this needs only
+    // tile-local offsets, so it runs before the look-back
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        const uint32_t d = digit_of(j);
+        rk[j] += s_tile_excl[d] + s_wcnt[wave * RADIX + d];
+        s_stage[rk[j]] = k[j];
+    }
+
+    // ---- look-back: the counts of this digit in the earlier tiles of the
+    // segment
+#pragma unroll
+    for (int i = 0; i < DPT; i++) {
+        const uint32_t d = tid * DPT + i;
+        if (d < (uint32_t)RADIX) {
+            uint32_t prefix = 0;
+            if (!first) {
+                prefix = look_back<RADIX>(status, tflag, tile, ti.first_tile, d, &a.counters[CTR_ERROR]);
+                store_agent(&status[(uint64_t)tile * RADIX + d], FLAG_INC | (prefix + tcnt[i]));
+            }
+            s_gbase[d] = ti.base + ti.excl[d] + prefix - texcl[i];
+            store_agent(&status_next[(uint64_t)tile * RADIX + d], 0u);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        store_agent(&tflag[tile], 1u);
+        store_agent(&tflag_next[tile], 0u);
+    }
+
+    // ---- contiguous runs of each digit go to their global offsets
+    uint32_t dest[PAIRS ? IPT : 1];
+    bool bad = false;
+#pragma unroll
+    for (int m = 0; m < IPT; m++) {
+        const uint32_t i = m * NT + tid;
+        if (PAIRS) dest[m] = n;
+        if (i < valid) {
+            const K key = s_stage[i];
+            const uint32_t g = s_gbase[dg(key)] + i;
+            if (g < n) {
+                dst[g] = key;
+                if (PAIRS) dest[m] = g;
+            } else {
+                bad = true;
+            }
+        }
+    }
+    if (bad) atomicOr(&a.counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
+    if (PAIRS) {
+        uint32_t *s_v = reinterpret_cast<uint32_t *>(s_raw);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; j++) s_v[rk[j]] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < IPT; m++) {
+            const uint32_t i = m * NT + tid;
+            if (i < valid && dest[m] < n) vdst[dest[m]] = s_v[i];
+        }
+    }
+}
+
+}  // namespace intsort

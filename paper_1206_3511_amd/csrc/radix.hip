@@ -32,27 +32,9 @@
 #include "device_common.hpp"
 #include "intsort.h"
 #include "internal.hpp"
+#include "onesweep.hpp"
 
 namespace intsort {
-
-template <typename K>
-__device__ __forceinline__ uint32_t digit_at(K k, uint32_t shift, uint32_t mask)
-{
-    return (uint32_t)(k >> shift) & mask;
-}
-
-// tile shape of the pass kernel for a key type and digit width
-template <typename K, int BITS>
-struct PassCfg {
-    static constexpr int WAVES = (BITS > 8) ? 4 : 8;
-    // keys per thread: large tiles keep the number of tiles, and with it the
-    // look-back traffic between them, small
-    static constexpr int IPT = sizeof(K) == 4 ? (BITS > 8 ? 16 : 32) : 16;
-    static constexpr int NT = WAVES * WAVE;
-    static constexpr int TILE = NT * IPT;
-    static constexpr int RADIX = 1 << BITS;
-    static constexpr int PASSES = (8 * (int)sizeof(K) + BITS - 1) / BITS;
-};
 
 constexpr int HIST_THREADS = 256;
 #ifndef HIST_UNROLL
@@ -64,14 +46,6 @@ constexpr int HIST_THREADS = 256;
 #ifndef HIST_COPIES
 #define HIST_COPIES 4
 #endif
-constexpr uint32_t LOOKBACK_SPIN_LIMIT = 1u << 20;
-#ifndef LOOKBACK_WINDOW
-#define LOOKBACK_WINDOW 4
-#endif
-#ifndef LOOKBACK_SPAN
-#define LOOKBACK_SPAN 32
-#endif
-
 // ------------------------------------------------------------------ init
 
 __global__ __launch_bounds__(256) void k_init(uint32_t *__restrict__ counters,
@@ -244,327 +218,6 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_plan(HistArgs a)
     }
 }
 
-// ------------------------------------------------------------- one pass
-
-template <typename K>
-struct PassArgs {
-    const K *in;
-    K *out;
-    K *tmp;
-    const uint32_t *vin;
-    uint32_t *vout;
-    uint32_t *vtmp;
-    const uint32_t *excl;   // this pass's exclusive digit offsets [radix]
-    const uint32_t *plan;   // this pass's plan words
-    uint32_t *status0;      // look-back words for even / odd active passes
-    uint32_t *status1;
-    uint32_t *counters;
-    uint32_t n;
-    uint32_t shift;
-    uint32_t pass;
-    uint32_t num_tiles;
-};
-
-// Sum of the counts of digit d in tiles 0 .. tile-1.
-//
-// Every tile publishes, per digit, an aggregate word (its own count) and
-// later an inclusive word (count of all tiles up to and including it); after
-// its inclusive words it also raises a per-tile flag.  The walk first reads
-// the flags of the 64 previous tiles (one load per lane) to find the nearest
-// tile that has finished, then fetches the status words of the whole span to
-// it in one batch.  The flag is only a hint: the status words alone decide,
-// and when the hint is missing, stale or too far away the walk falls back to
-// reading LOOKBACK_WINDOW words per round trip: aggregates are added and the
-// walk goes on, an inclusive word ends it, an unpublished word is polled
-// again (bounded: on timeout an error bit is set).
-template <int RADIX>
-__device__ __forceinline__ uint32_t look_back(const uint32_t *status, const uint32_t *tflag, uint32_t tile,
-                                              uint32_t d, uint32_t *err)
-{
-    constexpr int W = LOOKBACK_WINDOW;
-    constexpr int SPAN = LOOKBACK_SPAN;
-    uint32_t prefix = 0;
-    int64_t t = (int64_t)tile - 1;
-    {
-        const int64_t q = (int64_t)tile - 1 - (int64_t)lane_id();
-        const bool f = q >= 0 && load_agent(&tflag[q]) != 0u;
-        const uint64_t m = ballot(f);
-        if (m != 0) {
-            // lanes read tiles tile-1, tile-2, ...: the lowest set lane is
-            // the nearest finished tile
-            const int span = __builtin_ctzll(m) + 1;   // words tile-1 down to that tile
-            if (span <= SPAN) {
-                uint32_t sw[SPAN];
-#pragma unroll
-                for (int k = 0; k < SPAN; k++)
-                    sw[k] = k < span ? load_agent(&status[(uint64_t)(t - k) * RADIX + d]) : 0u;
-                bool stop = false, done = false;
-                int consumed = 0;
-#pragma unroll
-                for (int k = 0; k < SPAN; k++) {
-                    if (!stop && k < span) {
-                        const uint32_t fl = sw[k] >> FLAG_SHIFT;
-                        if (fl == 0) {
-                            stop = true;
-                        } else {
-                            prefix += sw[k] & COUNT_MASK;
-                            consumed++;
-                            if (fl & 2u) { stop = true; done = true; }
-                        }
-                    }
-                }
-                if (done) return prefix;
-                t -= consumed;
-            }
-        }
-    }
-    uint32_t spins = 0;
-    while (t >= 0) {
-        uint32_t s[W];
-#pragma unroll
-        for (int w = 0; w < W; w++) {
-            const int64_t tt = t - w;
-            // below tile 0 reads as an empty inclusive word (tile 0 always
-            // publishes an inclusive word, so a correct walk stops earlier)
-            s[w] = tt >= 0 ? load_agent(&status[(uint64_t)tt * RADIX + d]) : FLAG_INC;
-        }
-        bool stop = false, done = false;
-        int consumed = 0;
-#pragma unroll
-        for (int w = 0; w < W; w++) {
-            if (!stop) {
-                const uint32_t f = s[w] >> FLAG_SHIFT;
-                if (f == 0) {
-                    stop = true;
-                } else {
-                    prefix += s[w] & COUNT_MASK;
-                    consumed++;
-                    if (f & 2u) { stop = true; done = true; }
-                }
-            }
-        }
-        if (done) return prefix;
-        t -= consumed;
-        if (t < 0) break;
-        if (consumed == 0) {
-            if (++spins > LOOKBACK_SPIN_LIMIT) { atomicOr(err, DEVERR_LOOKBACK_TIMEOUT); return prefix; }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    atomicOr(err, DEVERR_BAD_TILE);
-    return prefix;
-}
-
-template <typename K, int BITS, bool PAIRS>
-__global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K> a)
-{
-    using C = PassCfg<K, BITS>;
-    constexpr int RADIX = C::RADIX, NT = C::NT, WAVES = C::WAVES, IPT = C::IPT, TILE = C::TILE;
-    constexpr uint32_t MASK = RADIX - 1;
-    constexpr int BM = BITS > 8 ? 256 : RADIX;          // peer bitmap words per wave
-    constexpr int DPT = RADIX > NT ? RADIX / NT : 1;    // digits per thread in digit phases
-    static_assert(TILE * sizeof(K) >= WAVES * BM * sizeof(uint64_t), "bitmaps alias the stage");
-    static_assert(RADIX <= NT * DPT, "digit phase covers every digit");
-
-    __shared__ alignas(16) unsigned char s_raw[TILE * sizeof(K)];
-    __shared__ uint32_t s_wcnt[WAVES * RADIX];
-    __shared__ uint32_t s_tile_excl[RADIX];
-    __shared__ uint32_t s_gbase[RADIX];
-    __shared__ uint32_t s_scan[NT / WAVE + 1];
-    __shared__ uint32_t s_tile;
-    K *s_stage = reinterpret_cast<K *>(s_raw);
-    uint64_t *s_bits = reinterpret_cast<uint64_t *>(s_raw);
-
-    if (a.plan[0] == 0) return;   // pass skipped: the same for every workgroup
-    const uint32_t srcc = a.plan[1], dstc = a.plan[2], ord = a.plan[3];
-    const K *src = srcc == BUF_IN ? a.in : (srcc == BUF_OUT ? a.out : a.tmp);
-    K *dst = dstc == BUF_OUT ? a.out : a.tmp;
-    const uint32_t *vsrc = nullptr;
-    uint32_t *vdst = nullptr;
-    if (PAIRS) {
-        vsrc = srcc == BUF_IN ? a.vin : (srcc == BUF_OUT ? a.vout : a.vtmp);
-        vdst = dstc == BUF_OUT ? a.vout : a.vtmp;
-    }
-    uint32_t *status = (ord & 1) ? a.status1 : a.status0;
-    uint32_t *status_next = (ord & 1) ? a.status0 : a.status1;
-    // per-tile "inclusive words published" flags follow each status array
-    uint32_t *tflag = status + (uint64_t)a.num_tiles * RADIX;
-    uint32_t *tflag_next = status_next + (uint64_t)a.num_tiles * RADIX;
-
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = lane_id();
-    const uint32_t wave = tid / WAVE;
-    const uint32_t shift = a.shift;
-    const uint32_t n = a.n;
-
-    for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
-    for (uint32_t i = tid; i < (uint32_t)(WAVES * BM); i += NT) s_bits[i] = 0;
-    if (tid == 0) s_tile = atomicAdd(&a.counters[CTR_TILE + a.pass], 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile >= a.num_tiles) {   // only if the counters were not reset: never index past the arrays
-        if (tid == 0) atomicOr(&a.counters[CTR_ERROR], DEVERR_BAD_TILE);
-        return;
-    }
-    const uint32_t base = tile * (uint32_t)TILE;
-    const uint32_t valid = min((uint32_t)TILE, n - base);
-
-    // ---- load: wave-striped, so (wave, item, lane) order is index order
-    K k[IPT];
-    uint32_t v[PAIRS ? IPT : 1];
-    const uint32_t wofs = base + wave * (IPT * WAVE) + lane;
-    if (valid == (uint32_t)TILE) {
-#pragma unroll
-        for (int j = 0; j < IPT; j++) {
-            k[j] = src[wofs + j * WAVE];
-            if (PAIRS) v[j] = vsrc[wofs + j * WAVE];
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < IPT; j++) {
-            const uint32_t idx = wofs + j * WAVE;
-            // keys past the end take the largest digit, so they rank last
-            k[j] = idx < n ? src[idx] : ~K(0);
-            if (PAIRS) v[j] = idx < n ? vsrc[idx] : 0u;
-        }
-    }
-
-    // ---- stable rank inside the wave: peers with the same digit come from a
-    // per-wave LDS bitmap that every lane ORs its bit into
-    uint32_t rk[IPT];
-    uint32_t *wcnt = s_wcnt + wave * RADIX;
-    uint64_t *bits = s_bits + wave * BM;
-    const uint64_t lanebit = 1ull << lane;
-#pragma unroll
-    for (int j = 0; j < IPT; j++) {
-        const uint32_t d = digit_at<K>(k[j], shift, MASK);
-        const uint32_t d0 = first_lane_value(d);
-        if (ballot(d != d0) == 0) {
-            const uint32_t c = wcnt[d0];
-            rk[j] = c + lane;
-            wave_sync();
-            if (lane == 0) wcnt[d0] = c + WAVE;
-            wave_sync();
-        } else {
-            const uint32_t h = BITS > 8 ? (d & 255u) : d;
-            atomicOr(reinterpret_cast<unsigned long long *>(&bits[h]), (unsigned long long)lanebit);
-            wave_sync();
-            uint64_t peers = __hip_atomic_load(&bits[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            if (BITS > 8) {
-#pragma unroll
-                for (int b = 8; b < BITS; b++) {
-                    const bool on = (d >> b) & 1u;
-                    const uint64_t bb = ballot(on);
-                    peers &= on ? bb : ~bb;
-                }
-            }
-            const uint32_t below = mbcnt(peers);
-            const uint32_t c = wcnt[d];
-            rk[j] = c + below;
-            wave_sync();
-            if (below == 0) {
-                wcnt[d] = c + popc64(peers);
-                __hip_atomic_store(&bits[h], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            }
-            wave_sync();
-        }
-    }
-    __syncthreads();
-
-    // ---- per digit: offsets of every wave inside the tile and the tile's
-    // count, published at once so that later tiles can look back over it
-    uint32_t tcnt[DPT];
-    uint32_t mine = 0;
-#pragma unroll
-    for (int i = 0; i < DPT; i++) {
-        const uint32_t d = tid * DPT + i;
-        tcnt[i] = 0;
-        if (d < (uint32_t)RADIX) {
-            uint32_t run = 0;
-#pragma unroll
-            for (int w = 0; w < WAVES; w++) {
-                const uint32_t c = s_wcnt[w * RADIX + d];
-                s_wcnt[w * RADIX + d] = run;
-                run += c;
-            }
-            tcnt[i] = run;
-            store_agent(&status[(uint64_t)tile * RADIX + d], (tile == 0 ? FLAG_INC : FLAG_AGG) | run);
-        }
-        mine += tcnt[i];
-    }
-    uint32_t total_unused;
-    uint32_t texcl[DPT];
-    texcl[0] = block_exclusive_scan<NT>(mine, s_scan, &total_unused);
-#pragma unroll
-    for (int i = 0; i < DPT; i++) {
-        const uint32_t d = tid * DPT + i;
-        if (i > 0) texcl[i] = texcl[i - 1] + tcnt[i - 1];
-        if (d < (uint32_t)RADIX) s_tile_excl[d] = texcl[i];
-    }
-    __syncthreads();
-
-    // ---- reorder the tile through LDS into digit order; this needs only
-    // tile-local offsets, so it runs before the look-back
-#pragma unroll
-    for (int j = 0; j < IPT; j++) {
-        const uint32_t d = digit_at<K>(k[j], shift, MASK);
-        rk[j] += s_tile_excl[d] + s_wcnt[wave * RADIX + d];
-        s_stage[rk[j]] = k[j];
-    }
-
-    // ---- look-back: the counts of this digit in all earlier tiles
-#pragma unroll
-    for (int i = 0; i < DPT; i++) {
-        const uint32_t d = tid * DPT + i;
-        if (d < (uint32_t)RADIX) {
-            uint32_t prefix = 0;
-            if (tile > 0) {
-                prefix = look_back<RADIX>(status, tflag, tile, d, &a.counters[CTR_ERROR]);
-                store_agent(&status[(uint64_t)tile * RADIX + d], FLAG_INC | (prefix + tcnt[i]));
-            }
-            s_gbase[d] = a.excl[d] + prefix - texcl[i];
-            store_agent(&status_next[(uint64_t)tile * RADIX + d], 0u);
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        store_agent(&tflag[tile], 1u);
-        store_agent(&tflag_next[tile], 0u);
-    }
-
-    // ---- contiguous runs of each digit go to their global offsets
-    uint32_t dest[PAIRS ? IPT : 1];
-    bool bad = false;
-#pragma unroll
-    for (int m = 0; m < IPT; m++) {
-        const uint32_t i = m * NT + tid;
-        if (PAIRS) dest[m] = n;
-        if (i < valid) {
-            const K key = s_stage[i];
-            const uint32_t g = s_gbase[digit_at<K>(key, shift, MASK)] + i;
-            if (g < n) {
-                dst[g] = key;
-                if (PAIRS) dest[m] = g;
-            } else {
-                bad = true;
-            }
-        }
-    }
-    if (bad) atomicOr(&a.counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
-    if (PAIRS) {
-        uint32_t *s_v = reinterpret_cast<uint32_t *>(s_raw);
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IPT; j++) s_v[rk[j]] = v[j];
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < IPT; m++) {
-            const uint32_t i = m * NT + tid;
-            if (i < valid && dest[m] < n) vdst[dest[m]] = s_v[i];
-        }
-    }
-}
-
 // ------------------------------------------------------------- final copy
 
 template <typename K, bool PAIRS>
@@ -706,15 +359,16 @@ static hipError_t run_typed(const RadixCall &c, hipStream_t s)
     a.status1 = reinterpret_cast<uint32_t *>(ws + L.status1);
     a.counters = reinterpret_cast<uint32_t *>(ws + L.counters);
     a.n = (uint32_t)c.n;
-    a.num_tiles = (uint32_t)L.num_tiles;
+    a.tile_capacity = (uint32_t)L.num_tiles;
     const uint32_t *excl = reinterpret_cast<const uint32_t *>(ws + L.excl);
     const uint32_t *plan = reinterpret_cast<const uint32_t *>(ws + L.plan);
     for (int p = 0; p < C::PASSES && p < c.max_passes; p++) {
-        a.excl = excl + p * C::RADIX;
         a.plan = plan + p * PLAN_WORDS;
-        a.shift = (uint32_t)(p * BITS);
         a.pass = (uint32_t)p;
-        hipLaunchKernelGGL((k_onesweep<K, BITS, PAIRS>), dim3((uint32_t)L.num_tiles), dim3(C::NT), 0, s, a);
+        const RadixDigit dg{(uint32_t)(p * BITS), (uint32_t)(C::RADIX - 1)};
+        const PlainTiles tl{(uint32_t)c.n, (uint32_t)L.num_tiles, excl + p * C::RADIX};
+        hipLaunchKernelGGL((k_onesweep<K, BITS, PAIRS, RadixDigit, PlainTiles>), dim3((uint32_t)L.num_tiles),
+                           dim3(C::NT), 0, s, a, dg, tl);
         if (c.timer) c.timer->mark(INTSORT_KERNEL_PASS, (uint32_t)p, s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -1,0 +1,318 @@
+// segmented.hip -- sorts every segment [offsets[s], offsets[s+1]) of a packed
+// array on its own, with no host read-back of the segment sizes.
+//
+// The offsets live on the device, so the device itself splits the segments
+// into size classes:
+//   tiny / small / medium / big   sorted by one workgroup each, entirely in
+//                                 LDS (k_lds_sort), reading the input and
+//                                 writing the output once;
+//   large                         cut into tiles that get consecutive ids;
+//                                 per-tile digit counts are summed per
+//                                 segment into digit offsets, then every
+//                                 digit pass runs k_onesweep over the tile
+//                                 list with its look-back bounded by the
+//                                 segment's first tile.
+// Every launch has a grid sized for the most work the class can hold; work
+// groups past the class's device-side count return at once.  Each segment is
+// sorted with the stable LSD radix sort of section 2.5 (Algorithm 4), so the
+// result is the segment's unique stable order.
+
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "device_common.hpp"
+#include "intsort.h"
+#include "internal.hpp"
+#include "lds_sort.hpp"
+#include "onesweep.hpp"
+#include "sort_plans.hpp"
+
+namespace intsort {
+
+// size classes of the segmented sort: capacity of one workgroup each
+template <typename K>
+struct SegClasses {
+    static constexpr int NCLASS = 4;
+    static constexpr uint32_t CAP0 = 64 * 4;       // one wave
+    static constexpr uint32_t CAP1 = 256 * 8;
+    static constexpr uint32_t CAP2 = 512 * 16;
+    static constexpr uint32_t CAP3 = sizeof(K) == 4 ? 512 * 32 : 512 * 16;
+    static constexpr uint32_t LDS_MAX = CAP3;      // above: the multi-workgroup path
+};
+
+constexpr int SEG_HIST_THREADS = 256;
+
+struct SegWs {
+    uint32_t *counters;
+    uint32_t *plan;
+    uint32_t *lists;          // [NCLASS][list_stride]
+    uint32_t list_stride;
+    uint32_t *slot_first;     // [slots] first tile id of every large segment
+    uint32_t *slot_ntiles;    // [slots]
+    TileDesc *tiles;          // [tile_cap]
+    uint32_t *tile_hist;      // [tile_cap][passes][256]
+    uint32_t *seg_excl;       // [passes][slot_cap][256]
+    uint32_t *status0;
+    uint32_t *status1;
+    uint32_t tile_cap;
+    uint32_t slot_cap;
+};
+
+// One thread per segment: classify by size; a large segment reserves a run
+// of consecutive tile ids and writes their descriptors.  Thread 0 also writes
+// the plan of the digit passes (all of them run; the last lands in the
+// output buffer).
+template <typename K>
+__global__ __launch_bounds__(256) void k_seg_classify(const uint64_t *__restrict__ offsets, uint64_t num_segments,
+                                                      SegWs w, uint32_t passes, uint32_t in_place)
+{
+    using CL = SegClasses<K>;
+    constexpr uint32_t TILE = PassCfg<K, 8>::TILE;
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0) {
+        uint32_t prev = BUF_IN;
+        for (uint32_t q = 0; q < passes; q++) {
+            uint32_t *pw = w.plan + q * PLAN_WORDS;
+            const uint32_t dst = in_place ? ((q % 2 == 0) ? BUF_TMP : BUF_OUT)
+                                          : (((passes - 1 - q) % 2 == 0) ? BUF_OUT : BUF_TMP);
+            pw[0] = 1; pw[1] = prev; pw[2] = dst; pw[3] = q;
+            prev = dst;
+        }
+    }
+    if (s >= num_segments) return;
+    const uint64_t lo = offsets[s], hi = offsets[s + 1];
+    const uint32_t m = hi > lo ? (uint32_t)(hi - lo) : 0u;
+    int cls;
+    if (m <= CL::CAP0) cls = 0;
+    else if (m <= CL::CAP1) cls = 1;
+    else if (m <= CL::CAP2) cls = 2;
+    else if (m <= CL::CAP3) cls = 3;
+    else cls = 4;
+    if (cls < 4) {
+        const uint32_t at = atomicAdd(&w.counters[CTR_SEG_CLASS + cls], 1u);
+        if (at < w.list_stride) w.lists[cls * w.list_stride + at] = (uint32_t)s;
+        return;
+    }
+    const uint32_t nt = (m + TILE - 1) / TILE;
+    const uint32_t slot = atomicAdd(&w.counters[CTR_SEG_SLOTS], 1u);
+    const uint32_t first = atomicAdd(&w.counters[CTR_SEG_TILES], nt);
+    if (slot >= w.slot_cap || first + nt > w.tile_cap) {   // sized on the host so that this cannot happen
+        atomicOr(&w.counters[CTR_ERROR], DEVERR_BAD_TILE);
+        return;
+    }
+    w.slot_first[slot] = first;
+    w.slot_ntiles[slot] = nt;
+    for (uint32_t t = 0; t < nt; t++) {
+        TileDesc d;
+        d.slot = slot;
+        d.first_tile = first;
+        d.start = (uint32_t)lo + t * TILE;
+        d.count = min(TILE, m - t * TILE);
+        d.base = (uint32_t)lo;
+        d.pad[0] = d.pad[1] = d.pad[2] = 0;
+        w.tiles[first + t] = d;
+    }
+}
+
+// per listed tile: the digit counts of every pass (one read of its keys);
+// also clears the tile's look-back words for the first pass
+template <int RADIX>
+__device__ __forceinline__ void seg_hist_add(uint32_t *s_h, uint32_t d)
+{
+    const uint32_t d0 = first_lane_value(d);
+    const uint64_t act = ballot(true);
+    if (ballot(d != d0) == 0) {
+        if (mbcnt(act) == 0) atomicAdd(&s_h[d0], popc64(act));
+    } else {
+        atomicAdd(&s_h[d], 1u);
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__restrict__ keys, SegWs w)
+{
+    constexpr int PASSES = (int)sizeof(K);
+    __shared__ uint32_t s_h[PASSES * 256];
+    const uint32_t t = blockIdx.x;
+    if (t >= w.counters[CTR_SEG_TILES]) return;
+    const TileDesc d = w.tiles[t];
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS) s_h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < 256u; i += SEG_HIST_THREADS) w.status0[(uint64_t)t * 256 + i] = 0;
+    if (threadIdx.x == 0) w.status0[(uint64_t)w.tile_cap * 256 + t] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < d.count; i += SEG_HIST_THREADS) {
+        const K k = keys[d.start + i];
+#pragma unroll
+        for (int p = 0; p < PASSES; p++) seg_hist_add<256>(s_h + p * 256, digit_at<K>(k, 8u * p, 0xffu));
+    }
+    __syncthreads();
+    uint32_t *out = w.tile_hist + (uint64_t)t * PASSES * 256;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS) out[i] = s_h[i];
+}
+
+// per large segment: sum its tiles' counts, exclusive scan per pass
+template <typename K>
+__global__ __launch_bounds__(256) void k_seg_scan(SegWs w)
+{
+    constexpr int PASSES = (int)sizeof(K);
+    __shared__ uint32_t s_scan[256 / WAVE + 1];
+    const uint32_t slot = blockIdx.x;
+    if (slot >= w.counters[CTR_SEG_SLOTS] || slot >= w.slot_cap) return;
+    const uint32_t first = w.slot_first[slot], nt = w.slot_ntiles[slot];
+    const uint32_t d = threadIdx.x;
+    for (int p = 0; p < PASSES; p++) {
+        uint32_t c = 0;
+        for (uint32_t t = 0; t < nt; t++) c += w.tile_hist[((uint64_t)(first + t) * PASSES + p) * 256 + d];
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan<256>(c, s_scan, &total);
+        w.seg_excl[((uint64_t)p * w.slot_cap + slot) * 256 + d] = ex;
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+template <typename K, bool PAIRS>
+static SegLayout seg_layout_typed(uint64_t n, uint64_t S)
+{
+    using CL = SegClasses<K>;
+    constexpr uint32_t TILE = PassCfg<K, 8>::TILE;
+    constexpr int PASSES = (int)sizeof(K);
+    SegLayout L{};
+    L.slot_cap = (uint32_t)std::min<uint64_t>(S, n / (CL::LDS_MAX + 1) + 1);
+    L.tile_cap = (uint32_t)((n + TILE - 1) / TILE + L.slot_cap);
+    L.list_stride = (uint32_t)S;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
+    L.counters = take((size_t)CTR_WORDS * 4);
+    L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
+    L.lists = take((size_t)CL::NCLASS * S * 4);
+    L.slot_first = take((size_t)L.slot_cap * 4);
+    L.slot_ntiles = take((size_t)L.slot_cap * 4);
+    L.tiles = take((size_t)L.tile_cap * sizeof(TileDesc));
+    L.tile_hist = take((size_t)L.tile_cap * PASSES * 256 * 4);
+    L.seg_excl = take((size_t)PASSES * L.slot_cap * 256 * 4);
+    L.status0 = take((size_t)L.tile_cap * 257 * 4);
+    L.status1 = take((size_t)L.tile_cap * 257 * 4);
+    L.tmp_keys = take(n * sizeof(K));
+    L.tmp_vals = take(PAIRS ? n * 4 : 0);
+    L.total = off;
+    return L;
+}
+
+SegLayout segmented_layout(int key_bytes, bool pairs, uint64_t n, uint64_t num_segments, const intsort_options &)
+{
+    if (key_bytes == 4) return pairs ? seg_layout_typed<uint32_t, true>(n, num_segments)
+                                     : seg_layout_typed<uint32_t, false>(n, num_segments);
+    return pairs ? seg_layout_typed<uint64_t, true>(n, num_segments) : seg_layout_typed<uint64_t, false>(n, num_segments);
+}
+
+template <typename K, bool PAIRS, int NT, int IPT>
+static void launch_lds_class(const LdsSortArgs<K> &la, uint32_t grid, hipStream_t s)
+{
+    if (grid == 0) return;
+    hipLaunchKernelGGL((k_lds_sort<K, PAIRS, NT, IPT>), dim3(grid), dim3(NT), 0, s, la);
+}
+
+template <typename K, bool PAIRS>
+static hipError_t seg_run_typed(const SegCall &c, hipStream_t s)
+{
+    using CL = SegClasses<K>;
+    using PC = PassCfg<K, 8>;
+    constexpr int PASSES = (int)sizeof(K);
+    const SegLayout &L = c.L;
+    char *ws = c.ws;
+    Timer *tm = c.timer;
+    SegWs w{};
+    w.counters = reinterpret_cast<uint32_t *>(ws + L.counters);
+    w.plan = reinterpret_cast<uint32_t *>(ws + L.plan);
+    w.lists = reinterpret_cast<uint32_t *>(ws + L.lists);
+    w.list_stride = L.list_stride;
+    w.slot_first = reinterpret_cast<uint32_t *>(ws + L.slot_first);
+    w.slot_ntiles = reinterpret_cast<uint32_t *>(ws + L.slot_ntiles);
+    w.tiles = reinterpret_cast<TileDesc *>(ws + L.tiles);
+    w.tile_hist = reinterpret_cast<uint32_t *>(ws + L.tile_hist);
+    w.seg_excl = reinterpret_cast<uint32_t *>(ws + L.seg_excl);
+    w.status0 = reinterpret_cast<uint32_t *>(ws + L.status0);
+    w.status1 = reinterpret_cast<uint32_t *>(ws + L.status1);
+    w.tile_cap = L.tile_cap;
+    w.slot_cap = L.slot_cap;
+    const bool in_place = c.keys_in == c.keys_out;
+
+    if (tm) tm->start(s);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, w.counters, (uint64_t)CTR_WORDS, 0u);
+    const uint32_t cgrid = (uint32_t)((c.num_segments + 255) / 256);
+    hipLaunchKernelGGL((k_seg_classify<K>), dim3(cgrid), dim3(256), 0, s, c.offsets, c.num_segments, w,
+                       (uint32_t)PASSES, in_place ? 1u : 0u);
+    if (tm) tm->mark(INTSORT_KERNEL_PLAN, 0, s);
+
+    // the four on-chip classes
+    LdsSortArgs<K> la{};
+    la.in = static_cast<const K *>(c.keys_in);
+    la.out = static_cast<K *>(c.keys_out);
+    la.vin = c.vals_in;
+    la.vout = c.vals_out;
+    la.offsets = c.offsets;
+    const uint64_t S = c.num_segments;
+    auto grid_for = [&](uint32_t lo_exclusive) {
+        // at most this many segments can be longer than lo_exclusive
+        const uint64_t by_n = c.n / (uint64_t)(lo_exclusive + 1);
+        return (uint32_t)std::min<uint64_t>(S, lo_exclusive == 0 ? S : by_n);
+    };
+    la.list = w.lists + 0 * L.list_stride;
+    la.list_count = w.counters + CTR_SEG_CLASS + 0;
+    launch_lds_class<K, PAIRS, 64, 4>(la, grid_for(0), s);
+    la.list = w.lists + 1 * L.list_stride;
+    la.list_count = w.counters + CTR_SEG_CLASS + 1;
+    launch_lds_class<K, PAIRS, 256, 8>(la, grid_for(CL::CAP0), s);
+    la.list = w.lists + 2 * L.list_stride;
+    la.list_count = w.counters + CTR_SEG_CLASS + 2;
+    launch_lds_class<K, PAIRS, 512, 16>(la, grid_for(CL::CAP1), s);
+    if (CL::CAP3 > CL::CAP2) {
+        la.list = w.lists + 3 * L.list_stride;
+        la.list_count = w.counters + CTR_SEG_CLASS + 3;
+        launch_lds_class<K, PAIRS, 512, (CL::CAP3 > CL::CAP2 ? 32 : 16)>(la, grid_for(CL::CAP2), s);
+    }
+    if (tm) tm->mark(INTSORT_KERNEL_SEGMENT_SORT, 0, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    // the large segments: digit counts per tile, offsets per segment, passes
+    hipLaunchKernelGGL((k_seg_tile_hist<K>), dim3(L.tile_cap), dim3(SEG_HIST_THREADS), 0, s,
+                       static_cast<const K *>(c.keys_in), w);
+    if (tm) tm->mark(INTSORT_KERNEL_DIGIT_HISTOGRAM, 0, s);
+    hipLaunchKernelGGL((k_seg_scan<K>), dim3(L.slot_cap), dim3(256), 0, s, w);
+    if (tm) tm->mark(INTSORT_KERNEL_PLAN, 1, s);
+
+    PassArgs<K> a{};
+    a.in = static_cast<const K *>(c.keys_in);
+    a.out = static_cast<K *>(c.keys_out);
+    a.tmp = reinterpret_cast<K *>(ws + L.tmp_keys);
+    a.vin = c.vals_in;
+    a.vout = c.vals_out;
+    a.vtmp = reinterpret_cast<uint32_t *>(ws + L.tmp_vals);
+    a.status0 = w.status0;
+    a.status1 = w.status1;
+    a.counters = w.counters;
+    a.n = (uint32_t)c.n;
+    a.tile_capacity = L.tile_cap;
+    for (int p = 0; p < PASSES; p++) {
+        a.plan = w.plan + p * PLAN_WORDS;
+        a.pass = (uint32_t)p;
+        const RadixDigit dg{(uint32_t)(8 * p), 0xffu};
+        const SegTiles tl{w.tiles, w.counters + CTR_SEG_TILES, w.seg_excl + (uint64_t)p * L.slot_cap * 256, 256u};
+        hipLaunchKernelGGL((k_onesweep<K, 8, PAIRS, RadixDigit, SegTiles>), dim3(L.tile_cap), dim3(PC::NT), 0, s,
+                           a, dg, tl);
+        if (tm) tm->mark(INTSORT_KERNEL_PASS, (uint32_t)p, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t segmented_sort_run(const SegCall &c, hipStream_t s)
+{
+    if (c.opts.digit_bits != 8) return hipErrorNotSupported;
+    if (c.key_bytes == 4) return c.pairs ? seg_run_typed<uint32_t, true>(c, s) : seg_run_typed<uint32_t, false>(c, s);
+    return c.pairs ? seg_run_typed<uint64_t, true>(c, s) : seg_run_typed<uint64_t, false>(c, s);
+}
+
+}  // namespace intsort

@@ -10,11 +10,20 @@
 
 namespace intsort {
 
-constexpr uint32_t MAX_BUCKETS = 1u << 20;
+constexpr uint32_t MAX_BUCKETS = 1u << 16;
 constexpr uint64_t MAX_SEGMENTS = 1ull << 24;
 
+struct SegLayout {
+    size_t counters, plan, lists, slot_first, slot_ntiles, tiles, tile_hist, seg_excl, status0, status1;
+    size_t tmp_keys, tmp_vals, total;
+    uint32_t slot_cap, tile_cap, list_stride;
+};
+
 struct BucketLayout {
-    size_t counters, total;
+    size_t counters, plan, minmax, counts, subhist, excl, offsets, status0, status1, tmpb_keys, tmpb_vals, seg, total;
+    uint32_t buckets, bits, scatter_passes;
+    uint64_t num_tiles;
+    SegLayout S;
 };
 
 struct BucketCall {
@@ -28,14 +37,12 @@ struct BucketCall {
     intsort_options opts;
     BucketLayout L;
     char *ws;
+    Timer *timer;
 };
 
 BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_options &o);
 hipError_t bucket_sort_run(const BucketCall &c, hipStream_t s);
 
-struct SegLayout {
-    size_t counters, total;
-};
 
 struct SegCall {
     const void *keys_in;
@@ -50,6 +57,7 @@ struct SegCall {
     intsort_options opts;
     SegLayout L;
     char *ws;
+    Timer *timer;
 };
 
 SegLayout segmented_layout(int key_bytes, bool pairs, uint64_t n, uint64_t num_segments,

@@ -1,0 +1,88 @@
+"""GPU parity of bucket sort (HIP path through the C ABI) against the CPU
+oracle: the min/max and bucket-index steps, the stable scatter (buckets
+filled in input order, Algorithm 2 before its per-bucket sort), and the
+final sorted keys and values, bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_1206_3511_amd import intsort as I
+from gpu_util import dev, host, rand_keys
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("B", [1, 7, 256, 1000, 1024, 2048, 3000, 65536])
+@pytest.mark.parametrize("n", [1, 2, 17, 1000, 16385, 100_003])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_bucket_pairs_parity(B, n, dtype):
+    print(f"bucket pairs B={B} n={n} {np.dtype(dtype).name}", flush=True)
+    rng = np.random.default_rng(B * 7 + n)
+    keys = rand_keys(rng, n, dtype, hi=None if n % 2 else max(2, n // 3))
+    vals = np.arange(n, dtype=np.uint32)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=B)
+    ref = oracle.radix_lsd(keys, vals)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+    out = I.sort(dev(keys), algo="bucket", num_buckets=B)
+    np.testing.assert_array_equal(host(out), ref.keys)
+    assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("B", [7, 1024, 2048, 65536])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_bucket_scatter_intermediate(B, dtype):
+    """Stopping after the scatter gives the oracle's bucketed array: the
+    stable partition of the input by bucket index."""
+    n = 50_021
+    keys = rand_keys(np.random.default_rng(B), n, dtype)
+    vals = np.arange(n, dtype=np.uint32)
+    ref = oracle.bucket(keys, vals, num_buckets=B, want_intermediates=True)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=B, max_passes=1)
+    np.testing.assert_array_equal(host(ok), ref.scat_keys)
+    np.testing.assert_array_equal(host(ov), ref.scat_vals)
+
+
+@pytest.mark.parametrize("dist", range(7))
+@pytest.mark.parametrize("B", [1024, 65536])
+def test_bucket_distributions(dist, B):
+    n = (1 << 20) + 123
+    print(f"bucket dist={workloads.DISTRIBUTIONS[dist]} B={B}", flush=True)
+    keys = workloads.config2_keys(dist, n)
+    vals = np.arange(n, dtype=np.uint32)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=B)
+    ref = oracle.radix_lsd(keys, vals)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+
+
+def test_bucket_special_and_in_place():
+    for dtype in (np.uint32, np.uint64):
+        mx = int(np.iinfo(dtype).max)
+        special = [0, 1, 2**31 - 1, 2**31, 2**32 - 1] + ([2**63, mx - 1, mx] if dtype == np.uint64 else [])
+        a = np.tile(np.array(special, dtype=dtype), 2000)
+        np.random.default_rng(1).shuffle(a)
+        for B in (3, 1024, 65536):
+            t = dev(a)
+            I.sort(t, out=t, algo="bucket", num_buckets=B)
+            np.testing.assert_array_equal(host(t), np.sort(a))
+        same = np.full(10_000, 12345, dtype=dtype)
+        np.testing.assert_array_equal(host(I.sort(dev(same), algo="bucket")), same)
+
+
+def test_config1_bucket():
+    """1,000,000 uniform uint32 keys, seed 0, 1024 buckets."""
+    keys = workloads.config2_keys(0, 1_000_000, seed=0)
+    out = host(I.sort(dev(keys), algo="bucket", num_buckets=1024))
+    np.testing.assert_array_equal(out, oracle.bucket(keys, num_buckets=1024).keys)
+
+
+@pytest.mark.parametrize("dist", range(7))
+def test_config2_bucket_full_size(dist):
+    n = 100_000_000
+    print(f"bucket full size dist={workloads.DISTRIBUTIONS[dist]}", flush=True)
+    keys = workloads.config2_keys(dist, n)
+    out = host(I.sort(dev(keys), algo="bucket", num_buckets=1024))
+    np.testing.assert_array_equal(out, oracle.radix_lsd(keys).keys)
+    assert I.device_error(0) == 0
