@@ -1,13 +1,18 @@
 """Benchmark of the MI355X integer sort.
 
-One step = one complete sort (every kernel of the method) of one array that
-is already resident in HBM, out of place from a pristine input.  The default
-workload is the headline: 100,000,000 uint32 keys drawn uniformly from
-[0, 2^32) (seed 0), LSD radix sort with 8-bit digits (4 passes).
+One step = one complete sort (every kernel of the method) of data already
+resident in HBM, out of place from a pristine input.  The default workload is
+the headline: 100,000,000 uint32 keys drawn uniformly from [0, 2^32) (seed 0),
+LSD radix sort with 8-bit digits (4 passes).  It prints one JSON line with the
+throughput (Gkeys/s), the roofline figure of the dominant kernel (the digit
+pass), and the single-threaded CPU oracle timed on the same input.
 
-Prints one JSON line with the throughput (Gkeys/s), the roofline figure of the
-dominant kernel (the digit pass), and the single-threaded CPU oracle timed on
-a bounded sample of the same input.
+Other workloads (``--workload NAME``, or ``--workload all``; one JSON line
+each): the seven 100M-key distributions under radix and bucket sort, 100M
+uint64 keys with a uint32 payload (radix with 8- and 11-bit digits, bucket
+sort with 65536 buckets), the batched sort of 10,000 arrays against one launch
+per array, and the serving trace (Poisson arrivals) through the continuous-
+batching server against the plain one-request-per-launch path.
 """
 from __future__ import annotations
 
@@ -21,21 +26,301 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-WORKLOADS = {
-    # name: (distribution, n, key dtype, algo, digit bits)
-    "uniform_u32_100M_radix_r8": ("uniform", 100_000_000, "u32", "radix", 8),
-    "uniform_u32_100M_bucket": ("uniform", 100_000_000, "u32", "bucket", 8),
-    "uniform_u32_1M_radix_r8": ("uniform", 1_000_000, "u32", "radix", 8),
-}
+DISTS = ("uniform", "small", "mid", "sorted", "reverse", "swaps", "gaussian")
 
 
-def algorithmic_bytes(n: int, w: int, v: int, passes: int) -> dict:
-    """Irreducible HBM traffic of LSD radix with a one-read histogram:
-    the histogram reads every key once; every pass reads and writes every key
-    (and value) once."""
-    per_pass = 2 * n * (w + v)
-    return {"histogram": n * w, "pass": per_pass, "total": n * w + passes * per_pass}
+def _workloads():
+    w = {"uniform_u32_100M_radix_r8": ("plain", dict(dist=0, n=100_000_000, algo="radix", bits=8, B=0))}
+    w["config1_u32_1M_radix_r8"] = ("plain", dict(dist=0, n=1_000_000, algo="radix", bits=8, B=0))
+    w["config1_u32_1M_bucket_B1024"] = ("plain", dict(dist=0, n=1_000_000, algo="bucket", bits=8, B=1024))
+    for d, name in enumerate(DISTS):
+        w[f"config2_{name}_u32_100M_radix_r8"] = ("plain", dict(dist=d, n=100_000_000, algo="radix", bits=8, B=0))
+        w[f"config2_{name}_u32_100M_bucket_B1024"] = ("plain", dict(dist=d, n=100_000_000, algo="bucket", bits=8,
+                                                                    B=1024))
+    for v in ("full", "b40"):
+        for algo, bits, B in (("radix", 8, 0), ("radix", 11, 0), ("bucket", 8, 65536)):
+            tag = f"radix_r{bits}" if algo == "radix" else f"bucket_B{B}"
+            w[f"config3_{v}_u64pairs_100M_{tag}"] = ("pairs", dict(variant=v, n=100_000_000, algo=algo, bits=bits,
+                                                                   B=B))
+    w["config4_batched_10k"] = ("batched", {})
+    w["config5_serving"] = ("serving", {})
+    return w
+
+
+WORKLOADS = _workloads()
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps
+
+
+def _kernel_avgs(ctx, fn, steps):
+    """The same steps again with HIP events around every kernel, on the stream
+    the kernels run on: average milliseconds per kernel kind."""
+    ctx.timing(True)
+    ctx.kernel_times()
+    for _ in range(steps):
+        fn()
+    times = ctx.kernel_times()
+    ctx.timing(False)
+    per = {}
+    for kind, idx, t in times:
+        per.setdefault(kind, []).append(t)
+    return {k: sum(x) / len(x) for k, x in per.items()}
+
+
+def _roofline(kernel, bytes_per_launch, avg_ms, extra=None):
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": int(bytes_per_launch),
+         "avg_launch_ms": round(avg_ms, 5)}
+    if extra:
+        r.update(extra)
+    return r
+
+
+def _line(metric, value, unit, ms, steps, warmup, dtype, config, roofline=None, cpu=None, **extra):
+    d = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+         "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu}
+    d.update(extra)
+    return d
+
+
+def run_plain(name, p, args):
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1206_3511_amd import intsort as I
+
+    n, algo, bits, B = p["n"], p["algo"], p["bits"], p["B"]
+    print(f"bench[{name}]: generating {n} keys ({DISTS[p['dist']]})", file=sys.stderr, flush=True)
+    keys_h = workloads.config2_keys(p["dist"], n, seed=0 if p["dist"] == 0 else None)
+    keys = torch.from_numpy(keys_h).to("cuda:0")
+    out = torch.empty_like(keys)
+    ctx = I.context(0)
+    opts = dict(algo=algo, digit_bits=bits, num_buckets=B)
+    fn = lambda: I.sort(keys, out=out, **opts)  # noqa: E731
+    ms = _timed(fn, args.steps, args.warmup)
+    value = n / (ms * 1e-3) / 1e9
+    print(f"bench[{name}]: {ms:.4f} ms/sort, {value:.2f} Gkeys/s", file=sys.stderr, flush=True)
+    avg = _kernel_avgs(ctx, fn, args.steps)
+    w = 4
+    if algo == "radix":
+        passes = -(-32 // bits)
+        per_pass = 2 * n * w
+        total = n * w + passes * per_pass
+        roof = _roofline("k_onesweep (one digit pass)", per_pass, avg.get("pass", float("nan")),
+                         {"kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()},
+                          "sort_level_frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "algorithmic_bytes_per_sort": total})
+    else:
+        per_pass = 2 * n * w
+        roof = _roofline("k_onesweep<BucketDigit> (one bucket-scatter pass)", per_pass,
+                         avg.get("bucket_scatter", float("nan")),
+                         {"kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()}})
+    ok = bool(np.array_equal(out.cpu().numpy(), np.sort(keys_h)))
+    cpu = None
+    if not args.no_cpu_baseline and name == "uniform_u32_100M_radix_r8":
+        cpu = cpu_baseline(keys_h, algo, bits, B, args)
+    metric = "Gkeys/s at 100M uint32 (LSD radix, 8-bit digits)" if name == "uniform_u32_100M_radix_r8" else \
+        f"Gkeys/s ({algo}, {n} uint32 keys)"
+    return _line(metric, value, "Gkeys/s", ms, args.steps, args.warmup, "u32",
+                 {"workload": name, "n": n, "distribution": DISTS[p["dist"]], "algo": algo, "digit_bits": bits,
+                  "num_buckets": B or None}, roof, cpu, output_matches_library_sort=ok)
+
+
+def cpu_baseline(keys_h, algo, bits, B, args):
+    import oracle
+
+    n = keys_h.shape[0]
+    m = min(args.cpu_sample, n) if args.cpu_sample > 0 else n
+    sample = keys_h[:m].copy()
+    print(f"bench: CPU oracle on {m} keys", file=sys.stderr, flush=True)
+    runs, spent, best = 0, 0.0, float("inf")
+    while runs < 1 or (spent < args.cpu_seconds and runs < 20):
+        t0 = time.perf_counter()
+        if algo == "radix":
+            oracle.radix_lsd(sample, r=bits)
+        else:
+            oracle.bucket(sample, num_buckets=B or 1024)
+        dt = time.perf_counter() - t0
+        spent += dt
+        best = min(best, dt)
+        runs += 1
+    per = spent / runs
+    return {"value": round(m / per / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"{'all' if m == n else 'first'} {m} keys of the same input, single-threaded oracle "
+                      f"{algo} sort repeated {runs} times ({spent:.1f} s, mean {per:.3f} s, best {best:.3f} s)"}
+
+
+def run_pairs(name, p, args):
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1206_3511_amd import intsort as I
+
+    n, algo, bits, B = p["n"], p["algo"], p["bits"], p["B"]
+    print(f"bench[{name}]: generating", file=sys.stderr, flush=True)
+    kh, vh = workloads.config3_pairs(p["variant"], n)
+    k = torch.from_numpy(kh).to("cuda:0")
+    v = torch.from_numpy(vh).to("cuda:0")
+    ok_, ov_ = torch.empty_like(k), torch.empty_like(v)
+    ctx = I.context(0)
+    fn = lambda: I.sort_pairs(k, v, algo=algo, digit_bits=bits, num_buckets=B, out_keys=ok_, out_vals=ov_)  # noqa
+    steps = max(1, args.steps // 4)
+    ms = _timed(fn, steps, 1)
+    value = n / (ms * 1e-3) / 1e9
+    avg = _kernel_avgs(ctx, fn, steps)
+    kind = "pass" if algo == "radix" else "bucket_scatter"
+    roof = _roofline(f"k_onesweep (pairs, {algo})", 2 * n * 12, avg.get(kind, float("nan")),
+                     {"kernel_avg_ms": {kk: round(x, 5) for kk, x in avg.items()}})
+    order = np.argsort(kh, kind="stable")
+    good = bool(np.array_equal(ok_.cpu().numpy(), kh[order]) and np.array_equal(ov_.cpu().numpy(), vh[order]))
+    return _line(f"Gkeys/s ({algo} pairs, 100M uint64 keys + uint32 payload)", value, "Gkeys/s", ms, steps, 1,
+                 "u64+u32", {"workload": name, "n": n, "variant": p["variant"], "algo": algo, "digit_bits": bits,
+                             "num_buckets": B or None}, roof, None, output_matches_stable_library_sort=good)
+
+
+def run_batched(name, p, args):
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1206_3511_amd import intsort as I
+
+    print(f"bench[{name}]: generating 10,000 arrays", file=sys.stderr, flush=True)
+    keys, offsets = workloads.segmented_keys()
+    N = keys.size
+    k = torch.from_numpy(keys).to("cuda:0")
+    out = torch.empty_like(k)
+    offs = torch.from_numpy(offsets.view(np.int64)).to("cuda:0")
+    ctx = I.context(0)
+    fn = lambda: I.segmented_sort(k, offs, out_keys=out)  # noqa: E731
+    steps = max(1, args.steps // 4)
+    ms = _timed(fn, steps, 1)
+    value = N / (ms * 1e-3) / 1e9
+    avg = _kernel_avgs(ctx, fn, steps)
+    # the plain path: every array in its own buffer, one sort call each
+    arrs = [k[int(offsets[j]):int(offsets[j + 1])].clone() for j in range(len(offsets) - 1)]
+    outs = [torch.empty_like(a) for a in arrs]
+
+    def loop():
+        for a, b in zip(arrs, outs):
+            I.sort(a, out=b)
+    ms_loop = _timed(loop, 1, 1)
+    roof = _roofline("k_onesweep<SegTiles> (one digit pass of the large arrays)", 2 * N * 4,
+                     avg.get("pass", float("nan")), {"kernel_avg_ms": {kk: round(x, 5) for kk, x in avg.items()}})
+    return _line("Gkeys/s (batched segmented sort of 10,000 uint32 arrays)", value, "Gkeys/s", ms, steps, 1, "u32",
+                 {"workload": name, "arrays": len(offsets) - 1, "keys": int(N), "sizes": "log-uniform [16, 2^20)"},
+                 roof, None, per_array_loop={"value": round(N / (ms_loop * 1e-3) / 1e9, 3), "ms": round(ms_loop, 3)},
+                 speedup_vs_per_array_loop=round(ms_loop / ms, 2))
+
+
+def serve_trace(I, pool, outbufs, trace, mode, sample_every=0):
+    """Replays the trace through a server.  Requests arrive at their trace
+    times (open loop); each needs one of the preallocated output buffers, and
+    a request that finds none free waits for one (that wait counts in its
+    latency, which runs from arrival to the completion the driver observes).
+    Returns (throughput Gkeys/s, p50 s, p99 s, requests, keys, samples)."""
+    import numpy as np
+    import torch
+
+    t_arr, wid, nn, dd = trace
+    max_batch, slots = (64, 2) if mode == "batched" else (1, 1)
+    srv = I.Server(0, budget_bytes=64 << 30, max_batch=max_batch, slots=slots)
+    free = list(range(len(outbufs)))
+    lat, keys_done, live, samples = [], 0, {}, []
+    R = len(t_arr)
+    i = 0
+    t0 = time.perf_counter()
+    first = last = None
+    while i < R or live:
+        now = time.perf_counter() - t0
+        while i < R and t_arr[i] <= now and free:
+            b = free.pop()
+            n = int(nn[i])
+            src = pool[(int(wid[i]), int(dd[i]))][:n]
+            out = outbufs[b].view(src.dtype)[:n]
+            tk = srv.submit(src, out)
+            live[tk] = (i, b, out)
+            if first is None:
+                first = time.perf_counter()
+            i += 1
+        for tk, _ in srv.completed():
+            idx, b, out = live.pop(tk)
+            done = time.perf_counter()
+            lat.append(done - (t0 + t_arr[idx]))
+            keys_done += int(nn[idx])
+            if sample_every and idx % sample_every == 0 and len(samples) < 40:
+                samples.append((idx, out.clone()))
+            free.append(b)
+            last = done
+        time.sleep(0.0001)
+    srv.drain()
+    srv.close()
+    lat = np.array(lat)
+    span = (last - first) if (first and last) else float("nan")
+    return keys_done / span / 1e9, float(np.percentile(lat, 50)), float(np.percentile(lat, 99)), len(lat), \
+        keys_done, samples
+
+
+def run_serving(name, p, args):
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads
+    from paper_1206_3511_amd import intsort as I
+
+    seconds = args.serve_seconds
+    trace = workloads.serving_trace(rate=2000.0, seconds=seconds)
+    print(f"bench[{name}]: {len(trace[0])} requests over {seconds} s; building device pool", file=sys.stderr,
+          flush=True)
+    pool = {}
+    for wdt in (4, 8):
+        for d in range(7):
+            pool[(wdt, d)] = workloads.device_keys(d, 1 << 26, 7000 + 10 * d + wdt, wdt, "cuda:0")
+    # output buffers: each holds the largest request (2^26 keys of 8 bytes)
+    outbufs = [torch.empty(1 << 26, dtype=torch.uint64, device="cuda:0") for _ in range(args.serve_buffers)]
+    torch.cuda.synchronize()
+    res = {}
+    for mode in ("batched", "plain"):
+        print(f"bench[{name}]: {mode}", file=sys.stderr, flush=True)
+        thr, p50, p99, cnt, keys, samples = serve_trace(I, pool, outbufs, trace, mode,
+                                                        sample_every=100 if mode == "batched" else 0)
+        print(f"bench[{name}]: {mode}: {thr:.2f} Gkeys/s p50 {p50 * 1e3:.3f} ms p99 {p99 * 1e3:.3f} ms",
+              file=sys.stderr, flush=True)
+        res[mode] = {"gkeys_per_s": round(thr, 3), "p50_ms": round(p50 * 1e3, 3), "p99_ms": round(p99 * 1e3, 3),
+                     "requests": cnt, "keys": keys}
+        if mode == "batched":
+            bad = 0
+            for idx, out in samples[:40]:
+                src = pool[(int(trace[1][idx]), int(trace[3][idx]))][: int(trace[2][idx])]
+                got = out.cpu().numpy()
+                alone = I.sort(src).cpu().numpy()
+                ref = oracle.radix_lsd(src.cpu().numpy()).keys
+                bad += int(not (np.array_equal(got, ref) and got.tobytes() == alone.tobytes()))
+            res["checked_samples"] = min(40, len(samples))
+            res["sample_mismatches"] = bad
+    b = res["batched"]
+    return _line("Gkeys/s served (Poisson 2000 req/s, uint32/uint64, 1K-64M keys)", b["gkeys_per_s"], "Gkeys/s",
+                 float("nan"), 0, 0, "u32/u64",
+                 {"workload": name, "rate_per_s": 2000, "seconds": seconds, "budget_gb": 64, "max_batch": 64,
+                  "slots": 2, "output_buffers": args.serve_buffers}, None, None, serving=res,
+                 p50_ms=b["p50_ms"], p99_ms=b["p99_ms"], plain_path=res["plain"])
 
 
 def main():
@@ -43,128 +328,31 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="uniform_u32_100M_radix_r8", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="uniform_u32_100M_radix_r8",
+                    help="one of: " + ", ".join(sorted(WORKLOADS)) + ", or all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="keys of the same input that the CPU oracle sorts (0 = all of them)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU oracle sort until this much time has passed")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving trace")
+    ap.add_argument("--serve-buffers", type=int, default=96,
+                    help="preallocated output buffers of 512 MB each for the serving trace")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import workloads
-    from paper_1206_3511_amd import intsort as I
-
-    dist, n, kdt, algo, bits = WORKLOADS[args.workload]
-    assert kdt == "u32"
-    w, v = 4, 0
-    passes = -(-32 // bits)
-    print(f"bench: generating {n} keys ({dist}, seed 0)", file=sys.stderr, flush=True)
-    keys_h = workloads.config2_keys(dist, n, seed=0)
-    dev = torch.device("cuda:0")
-    keys = torch.from_numpy(keys_h).to(dev)
-    out = torch.empty_like(keys)
-    ctx = I.context(0)
-    opts = dict(algo=algo, digit_bits=bits)
-
-    print("bench: warmup", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        I.sort(keys, out=out, **opts)
-    torch.cuda.synchronize()
-
-    # ---- timed region: K whole sorts, no per-kernel events
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        I.sort(keys, out=out, **opts)
-    end.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
-    value = n / (ms * 1e-3) / 1e9
-    print(f"bench: {ms:.4f} ms/sort, {value:.2f} Gkeys/s", file=sys.stderr, flush=True)
-
-    # ---- the same K sorts again with HIP events around every kernel, on the
-    # stream the kernels run on: average duration of each kernel kind
-    ctx.timing(True)
-    ctx.kernel_times()
-    for _ in range(args.steps):
-        I.sort(keys, out=out, **opts)
-    times = ctx.kernel_times()
-    ctx.timing(False)
-    per_kind: dict[str, list[float]] = {}
-    for kind, idx, t in times:
-        per_kind.setdefault(kind, []).append(t)
-    avg = {k: sum(x) / len(x) for k, x in per_kind.items()}
-    ab = algorithmic_bytes(n, w, v, passes)
-    pass_ms = avg.get("pass", float("nan"))
-    achieved = ab["pass"] / (pass_ms * 1e-3) / 1e9
-    roofline = {
-        "bound": "hbm",
-        "kernel": "k_onesweep (one digit pass)",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
-        "bytes_per_launch": ab["pass"],
-        "avg_launch_ms": round(pass_ms, 5),
-        "kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()},
-        "sort_level_frac": round(ab["total"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-    }
-
-    # correctness of the timed output against a library sort of the same keys
-    ok = bool(np.array_equal(out.cpu().numpy(), np.sort(keys_h)))
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        m = min(args.cpu_sample, n) if args.cpu_sample > 0 else n
-        sample = keys_h[:m].copy()
-        print(f"bench: CPU oracle on {m} keys", file=sys.stderr, flush=True)
-        runs, spent, best = 0, 0.0, float("inf")
-        while runs < 1 or (spent < args.cpu_seconds and runs < 20):
-            t0 = time.perf_counter()
-            if algo == "radix":
-                oracle.radix_lsd(sample, r=bits)
-            else:
-                oracle.bucket(sample, num_buckets=1024)
-            dt = time.perf_counter() - t0
-            spent += dt
-            best = min(best, dt)
-            runs += 1
-        per = spent / runs
-        cpu = {"value": round(m / per / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-               "sample": f"{'all' if m == n else 'first'} {m} keys of the same input, single-threaded oracle "
-                         f"{algo} sort repeated {runs} times ({spent:.1f} s, mean {per:.3f} s, best {best:.3f} s)"}
-
-    line = {
-        "metric": "Gkeys/s at 100M uint32 (LSD radix, 8-bit digits)" if n == 100_000_000 else "Gkeys/s",
-        "value": round(value, 3),
-        "unit": "Gkeys/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "distribution": dist, "seed": 0, "algo": algo,
-                   "digit_bits": bits, "passes": passes},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "output_matches_library_sort": ok,
-    }
-    print(json.dumps(line), flush=True)
+    names = sorted(WORKLOADS) if args.workload == "all" else [args.workload]
+    for name in names:
+        if name not in WORKLOADS:
+            print(f"unknown workload {name}", file=sys.stderr)
+            sys.exit(2)
+        kind, p = WORKLOADS[name]
+        fn = {"plain": run_plain, "pairs": run_pairs, "batched": run_batched, "serving": run_serving}[kind]
+        print(json.dumps(fn(name, p, args)), flush=True)
+        import torch
+        torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

@@ -75,8 +75,8 @@ typedef enum intsort_algo {
  *   digit_bits   radix digit width r: 0 (default 8) | 4 | 8 | 11.  The
  *                number of passes is ceil(key_bits / r) (Algorithm 4's d
  *                for a key of key_bits bits).
- *   num_buckets  bucket sort: number of buckets B (default 1024 for u32,
- *                65536 for u64).  The bucket of key k is
+ *   num_buckets  bucket sort: number of buckets B, 1..65536 (default 1024
+ *                for u32, 65536 for u64).  The bucket of key k is
  *                floor((k - min) * B / (max - min + 1)), exact.
  *   lds_cutoff   bucket/segmented: segments of at most this many keys are
  *                sorted by one workgroup entirely in LDS (default: the
@@ -85,6 +85,9 @@ typedef enum intsort_algo {
  *                value p the output is the input stably sorted on its low
  *                p*r bits; this exposes the intermediate arrays of
  *                Algorithm 4.  Implies INTSORT_FLAG_NO_PASS_SKIP.
+ *                bucket: 1 stops after the scatter: the output holds every
+ *                bucket's keys in input order, buckets concatenated
+ *                (Algorithm 2 before its per-bucket sorts).
  *   flags        INTSORT_FLAG_*.
  */
 typedef struct intsort_options {
@@ -166,6 +169,65 @@ intsort_status intsort_segmented_sort_pairs(intsort_ctx *ctx, intsort_key_type k
                                             const uint64_t *d_offsets,
                                             const intsort_options *opts, void *workspace,
                                             size_t workspace_bytes, void *stream);
+
+/*
+ * One array of a batch: device input and output buffers (keys_in ==
+ * keys_out sorts in place) and the number of keys.  16-byte aligned bases.
+ */
+typedef struct intsort_segment_desc {
+    const void *keys_in;
+    void *keys_out;
+    uint64_t n;
+} intsort_segment_desc;
+
+/*
+ * Batched sort, the serving form of the segmented sort: `count` separate
+ * arrays of key type kt, described by the DEVICE array d_descs[count], are
+ * sorted in one set of launches; array i's keys_out receives the
+ * nondecreasing permutation of its keys_in.  total_keys must be at least the
+ * sum of all n (it sizes the work; the descriptors are not read on the host).
+ * The workspace is intsort_workspace_size(ctx, kt, 0, total_keys, count,
+ * opts, &bytes).  Keys only; 8-bit digits.
+ */
+intsort_status intsort_batched_sort_keys(intsort_ctx *ctx, intsort_key_type kt,
+                                         const intsort_segment_desc *d_descs, uint64_t count,
+                                         uint64_t total_keys, const intsort_options *opts,
+                                         void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Serving loop with continuous batching.  A server owns a worker thread and
+ * `slots` streams (1..4), each with a workspace for batches of up to 2^27
+ * keys, allocated once in intsort_server_create on the context's device.  Requests are (key type, device input, device output,
+ * n); the caller owns those arrays and must keep them alive until the
+ * request completes.  A request's footprint is 3*w*n + 4*n + 4096 bytes for
+ * w-byte keys (its two arrays plus its share of a batch workspace); one
+ * larger than hbm_budget_bytes, or with more than 2^27 keys, is refused with
+ * INTSORT_ERR_OVER_BUDGET.  Whenever a slot is free the worker admits waiting
+ * requests in arrival order while their footprints fit the budget next to
+ * the requests still running, launches them as one batched sort per key type
+ * (at most max_batch arrays each) and, when the batch's completion event has
+ * fired, marks them done with latency = completion seen by the worker -
+ * submission.  max_batch = 1 with slots = 1 is the plain one-request-per-
+ * launch path.
+ *
+ * intsort_server_poll: *done = 1 and INTSORT_OK when finished,
+ *   INTSORT_ERR_NOT_READY while waiting or running.
+ * intsort_server_completed: tickets (and latencies) finished since the last
+ *   call, oldest first, at most `capacity`; finished tickets are forgotten.
+ * intsort_server_drain: blocks until every submitted request has finished.
+ * intsort_server_destroy: drains, stops the worker, frees the workspaces.
+ */
+typedef struct intsort_server intsort_server;
+
+intsort_status intsort_server_create(intsort_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_batch,
+                                     uint32_t slots, intsort_server **server);
+intsort_status intsort_server_submit(intsort_server *server, intsort_key_type kt, const void *d_in,
+                                     void *d_out, uint64_t n, uint64_t *ticket);
+intsort_status intsort_server_poll(intsort_server *server, uint64_t ticket, int *done, double *latency_s);
+intsort_status intsort_server_completed(intsort_server *server, uint64_t *tickets, double *latency_s,
+                                        uint32_t capacity, uint32_t *count);
+intsort_status intsort_server_drain(intsort_server *server);
+intsort_status intsort_server_destroy(intsort_server *server);
 
 /*
  * Step-level entry points.  Each runs one step of the sorts above on its own

@@ -4,6 +4,6 @@ behind the C ABI of include/intsort.h.  Importing the package loads nothing;
 the first call loads libintsort.so (built by paper_1206_3511_amd/build.py)."""
 
 from .intsort import (  # noqa: F401
-    Context, IntsortError, bucket_histogram, context, device_error, digit_histogram, lib, make_options,
-    minmax, segmented_sort, sort, sort_pairs, status_string,
+    Context, IntsortError, Server, batched_sort, bucket_histogram, context, device_error, digit_histogram, lib,
+    make_options, minmax, segmented_sort, sort, sort_pairs, status_string,
 )

@@ -16,6 +16,8 @@ struct intsort_ctx {
     intsort::Timer *timer = nullptr;   // set while per-kernel timing is on
 };
 
+int intsort::ctx_device(const intsort_ctx *ctx) { return ctx ? ctx->device : -1; }
+
 namespace {
 
 using namespace intsort;
@@ -342,6 +344,7 @@ static intsort_status segmented_common(intsort_ctx *ctx, intsort_key_type kt, co
     c.n = n_total;
     c.num_segments = num_segments;
     c.offsets = d_offsets;
+    c.descs = nullptr;
     c.key_bytes = kb;
     c.pairs = pairs;
     c.opts = o;
@@ -373,6 +376,39 @@ intsort_status intsort_segmented_sort_pairs(intsort_ctx *ctx, intsort_key_type k
     try {
         return segmented_common(ctx, kt, keys_in, keys_out, vals_in, vals_out, true, n_total, num_segments,
                                 d_offsets, opts, workspace, workspace_bytes, stream);
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_batched_sort_keys(intsort_ctx *ctx, intsort_key_type kt, const intsort_segment_desc *d_descs,
+                                         uint64_t count, uint64_t total_keys, const intsort_options *opts,
+                                         void *workspace, size_t workspace_bytes, void *stream)
+{
+    try {
+        if (!ctx || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
+        intsort_options o;
+        intsort_status st = read_opts(opts, kt, &o);
+        if (st != INTSORT_OK) return st;
+        if (count == 0 || total_keys == 0) return INTSORT_OK;
+        if (!d_descs) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (o.digit_bits != 8) return INTSORT_ERR_UNSUPPORTED;
+        if (total_keys > MAX_KEYS || count > MAX_SEGMENTS) return INTSORT_ERR_UNSUPPORTED;
+        const int kb = key_bytes_of(kt);
+        const SegLayout L = segmented_layout(kb, false, total_keys, count, o);
+        if ((st = check_ws(workspace, workspace_bytes, L.total)) != INTSORT_OK) return st;
+        if ((st = set_device(ctx)) != INTSORT_OK) return st;
+        SegCall c{};
+        c.n = total_keys;
+        c.num_segments = count;
+        c.descs = d_descs;
+        c.key_bytes = kb;
+        c.pairs = false;
+        c.opts = o;
+        c.L = L;
+        c.ws = static_cast<char *>(workspace);
+        c.timer = ctx->timer;
+        return from_hip(segmented_sort_run(c, static_cast<hipStream_t>(stream)));
     } catch (...) {
         return INTSORT_ERR_INTERNAL;
     }

@@ -20,7 +20,8 @@ struct BucketMap {
     uint64_t mn;
     uint64_t range_m1;    // R - 1 = max - min (R itself may be 2^64)
     uint32_t buckets;     // B >= 1
-    double scale;         // B / R in double precision
+    double scale;         // B / R in double precision (64-bit keys)
+    uint64_t inv;         // floor((2^64 - 1) / R) (32-bit keys, R <= 2^32)
     bool full64;          // R == 2^64
 };
 
@@ -34,27 +35,23 @@ __device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, u
     // R as a double: exact for R <= 2^53, correctly rounded above
     const double R = m.full64 ? 18446744073709551616.0 : (double)m.range_m1 + 1.0;
     m.scale = (double)B / R;
+    m.inv = m.full64 ? 1ull : ~0ull / (m.range_m1 + 1);
     return m;
 }
 
-// b(k) for 32-bit keys: the numerator is below 2^52, so it and R are exact
-// doubles and a 64-bit remainder check fixes the estimate.  For a key inside
-// [min, max] at most one correction step is taken; the steps are bounded and
-// the result clamped so that a key outside the range cannot index past B.
+// b(k) for 32-bit keys.  num = (k - min) * B is below 2^48; with
+// inv = floor((2^64 - 1) / R) the estimate floor(num * inv / 2^64) is either
+// the exact quotient or one less (num * inv / 2^64 lies within num / 2^64 < 1
+// of num / R), so one remainder check makes it exact.  The result is clamped
+// so that a key outside [min, max] cannot index past B.
 __device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint32_t k)
 {
     const uint64_t x = (uint64_t)(k - (uint32_t)m.mn);
     const uint64_t num = x * (uint64_t)m.buckets;
     const uint64_t R = m.range_m1 + 1;   // <= 2^32 for 32-bit keys
-    int64_t q = (int64_t)((double)num * (1.0 / (double)R));
-    if (q >= (int64_t)m.buckets) q = (int64_t)m.buckets - 1;
-    // num - q*R must lie in [0, R)
-    int64_t rem = (int64_t)num - q * (int64_t)R;
-    for (int it = 0; it < 2 && rem < 0; it++) { q--; rem += (int64_t)R; }
-    for (int it = 0; it < 2 && rem >= (int64_t)R; it++) { q++; rem -= (int64_t)R; }
-    if (q < 0) q = 0;
-    if (q >= (int64_t)m.buckets) q = (int64_t)m.buckets - 1;
-    return (uint32_t)q;
+    uint64_t q = __umul64hi(num, m.inv);
+    if (num - q * R >= R) q++;
+    return (uint32_t)(q < m.buckets ? q : m.buckets - 1);
 }
 
 // b(k) for 64-bit keys: 128-bit products decide the exact floor

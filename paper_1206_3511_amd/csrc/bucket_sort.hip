@@ -55,50 +55,64 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
 // One workgroup: exclusive offsets of the scatter digit(s), the bucket
 // starts when the scatter is a single pass, and the plan words.
 struct BucketPlanArgs {
-    const uint32_t *counts;   // [B] (single pass)
-    const uint32_t *subhist;  // [2][256] (two passes)
+    const uint32_t *counts;   // [B], when the full histogram was taken
+    const uint32_t *subhist;  // [2][256], when only the byte histograms were
     uint32_t *excl;           // [passes][radix]
     uint64_t *offsets;        // [B + 1]
     uint32_t *plan;
     uint32_t B, radix, passes;
+    uint32_t full;            // counts holds the full histogram
     uint64_t n;
 };
 
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
 {
     __shared__ uint32_t s_scan[BK_THREADS / WAVE + 1];
+    __shared__ uint32_t s_byte[2 * 256];
     const uint32_t tid = threadIdx.x;
-    for (uint32_t p = 0; p < a.passes; p++) {
-        const uint32_t dpt = (a.radix + BK_THREADS - 1) / BK_THREADS;   // digits per thread, <= 8
-        uint32_t c[8];
+    if (a.full) {
+        // bucket starts: exclusive scan of the full histogram (B <= 16384:
+        // 64 buckets per thread at most)
+        const uint32_t per = (a.B + BK_THREADS - 1) / BK_THREADS;
         uint32_t mine = 0;
-        for (uint32_t i = 0; i < 8; i++) {
-            const uint32_t d = tid * dpt + i;
-            c[i] = 0;
-            if (i < dpt && d < a.radix) {
-                if (a.passes == 1) c[i] = d < a.B ? a.counts[d] : 0u;
-                else c[i] = a.subhist[p * 256 + d];
-            }
-            mine += c[i];
+        for (uint32_t i = 0; i < per; i++) {
+            const uint32_t b = tid * per + i;
+            if (b < a.B) mine += a.counts[b];
         }
         uint32_t total;
         uint32_t run = block_exclusive_scan<BK_THREADS>(mine, s_scan, &total);
-        for (uint32_t i = 0; i < dpt; i++) {
-            const uint32_t d = tid * dpt + i;
-            if (d < a.radix) {
-                a.excl[p * a.radix + d] = run;
-                if (a.passes == 1 && d < a.B) a.offsets[d] = run;
+        for (uint32_t i = 0; i < per; i++) {
+            const uint32_t b = tid * per + i;
+            if (b < a.B) {
+                a.offsets[b] = run;
+                run += a.counts[b];
             }
-            run += c[i];
         }
+        if (tid == 0) a.offsets[a.B] = a.n;
+        // counts of the low and the high byte of the bucket index
+        for (uint32_t i = tid; i < 512u; i += BK_THREADS) s_byte[i] = 0;
+        __syncthreads();
+        for (uint32_t b = tid; b < a.B; b += BK_THREADS) {
+            const uint32_t c = a.counts[b];
+            if (c) {
+                atomicAdd(&s_byte[b & 255u], c);
+                atomicAdd(&s_byte[256 + (b >> 8)], c);
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t p = 0; p < a.passes; p++) {
+        const uint32_t d = tid;   // radix 256: one digit per thread
+        const uint32_t c = a.full ? s_byte[p * 256 + d] : a.subhist[p * 256 + d];
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan<BK_THREADS>(c, s_scan, &total);
+        a.excl[p * a.radix + d] = ex;
     }
     if (tid == 0) {
+        uint32_t *w = a.plan;
         if (a.passes == 1) {
-            a.offsets[a.B] = a.n;
-            uint32_t *w = a.plan;
             w[0] = 1; w[1] = BUF_IN; w[2] = BUF_OUT; w[3] = 0;
         } else {
-            uint32_t *w = a.plan;
             w[0] = 1; w[1] = BUF_IN; w[2] = BUF_TMP; w[3] = 0;
             w += PLAN_WORDS;
             w[0] = 1; w[1] = BUF_TMP; w[2] = BUF_OUT; w[3] = 1;
@@ -151,7 +165,8 @@ __global__ __launch_bounds__(1024) void k_suffix_min(uint64_t *offsets, uint32_t
 
 // ------------------------------------------------------------------ host
 
-static uint32_t scatter_bits(uint32_t B) { return B <= 256 ? 8u : (B <= 2048 ? 11u : 8u); }
+static uint32_t scatter_bits(uint32_t) { return 8u; }
+constexpr uint32_t BUCKET_LDS_HIST_MAX = 16384;   // bucket_histogram_run's on-chip limit
 
 template <typename K>
 static uint64_t scatter_tile(uint32_t bits) { return bits == 11 ? PassCfg<K, 11>::TILE : PassCfg<K, 8>::TILE; }
@@ -161,7 +176,7 @@ BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_
     BucketLayout L{};
     L.buckets = o.num_buckets;
     L.bits = scatter_bits(L.buckets);
-    L.scatter_passes = L.buckets <= 2048 ? 1u : 2u;
+    L.scatter_passes = L.buckets <= 256 ? 1u : 2u;
     const uint64_t tile = key_bytes == 4 ? scatter_tile<uint32_t>(L.bits) : scatter_tile<uint64_t>(L.bits);
     L.num_tiles = (n + tile - 1) / tile;
     const uint64_t radix = 1ull << L.bits;
@@ -218,7 +233,8 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     hipError_t e = minmax_run((int)sizeof(K), c.keys_in, c.n, minmax, s);
     if (e != hipSuccess) return e;
     if (tm) tm->mark(INTSORT_KERNEL_MINMAX, 0, s);
-    if (L.scatter_passes == 1) {
+    const bool full_hist = B <= BUCKET_LDS_HIST_MAX;
+    if (full_hist) {
         e = bucket_histogram_run((int)sizeof(K), c.keys_in, c.n, minmax, B, counts, s);
     } else {
         hipLaunchKernelGGL(k_fill<uint32_t>, dim3(2), dim3(256), 0, s, subhist, (uint64_t)SUBHIST_WORDS, 0u);
@@ -229,7 +245,8 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     }
     if (e != hipSuccess) return e;
     if (tm) tm->mark(INTSORT_KERNEL_BUCKET_HISTOGRAM, 0, s);
-    BucketPlanArgs pa{counts, subhist, excl, offsets, plan, B, (uint32_t)C::RADIX, L.scatter_passes, c.n};
+    BucketPlanArgs pa{counts, subhist, excl, offsets, plan, B, (uint32_t)C::RADIX, L.scatter_passes,
+                      full_hist ? 1u : 0u, c.n};
     hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(BK_THREADS), 0, s, pa);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(fill_grid), dim3(256), 0, s, status0,
                        (uint64_t)L.num_tiles * (C::RADIX + 1), 0u);
@@ -260,7 +277,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (scatter_only) return hipSuccess;
 
-    if (L.scatter_passes == 2) {
+    if (!full_hist) {
         hipLaunchKernelGGL(k_fill<uint64_t>, dim3((B + 256) / 256), dim3(256), 0, s, offsets, (uint64_t)B + 1,
                            (uint64_t)c.n);
         uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
@@ -292,7 +309,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
 template <typename K, bool PAIRS>
 static hipError_t bucket_run_bits(const BucketCall &c, hipStream_t s)
 {
-    return c.L.bits == 11 ? bucket_run_typed<K, PAIRS, 11>(c, s) : bucket_run_typed<K, PAIRS, 8>(c, s);
+    return bucket_run_typed<K, PAIRS, 8>(c, s);
 }
 
 hipError_t bucket_sort_run(const BucketCall &c, hipStream_t s)

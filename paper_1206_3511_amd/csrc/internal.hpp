@@ -34,6 +34,7 @@ constexpr int CTR_ERROR = MAX_PASSES + 1;
 constexpr int CTR_SEG_CLASS = 32;   // [4] segments per on-chip size class
 constexpr int CTR_SEG_SLOTS = 36;   // large segments
 constexpr int CTR_SEG_TILES = 37;   // tiles of the large segments
+constexpr int CTR_SEG_TMP = 38;     // scratch keys handed out to large separate arrays
 constexpr int CTR_WORDS = 64;
 
 // HIP events around kernels (profiling only).  Events accumulate over calls
@@ -109,5 +110,13 @@ hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, con
                                 uint32_t num_buckets, uint32_t *counts, hipStream_t s);
 
 int device_cu_count(int device);
+
+}  // namespace intsort
+
+struct intsort_ctx;
+namespace intsort {
+
+// HIP device of a context (-1 for a planning context)
+int ctx_device(const intsort_ctx *ctx);
 
 }  // namespace intsort

@@ -12,24 +12,59 @@
 #include <stdint.h>
 
 #include "device_common.hpp"
+#include "intsort.h"
 #include "internal.hpp"
 #include "onesweep.hpp"
 
 namespace intsort {
 
-template <typename K>
-struct LdsSortArgs {
-    const K *in;
-    K *out;
+// where the keys of segment s live: one packed array cut by offsets ...
+struct PackedSrc {
+    const void *in;
+    void *out;
     const uint32_t *vin;
     uint32_t *vout;
     const uint64_t *offsets;     // [segments + 1]
+    template <typename K>
+    __device__ __forceinline__ void seg(uint64_t s, const K *&kin, K *&kout, const uint32_t *&vi, uint32_t *&vo,
+                                        uint32_t &m, uint32_t &base) const
+    {
+        const uint64_t lo = offsets[s], hi = offsets[s + 1];
+        m = hi > lo ? (uint32_t)(hi - lo) : 0u;
+        base = (uint32_t)lo;
+        kin = static_cast<const K *>(in) + lo;
+        kout = static_cast<K *>(out) + lo;
+        vi = vin ? vin + lo : nullptr;
+        vo = vout ? vout + lo : nullptr;
+    }
+};
+
+// ... or separate arrays, one descriptor each (keys only)
+struct DescSrc {
+    const intsort_segment_desc *d;
+    template <typename K>
+    __device__ __forceinline__ void seg(uint64_t s, const K *&kin, K *&kout, const uint32_t *&vi, uint32_t *&vo,
+                                        uint32_t &m, uint32_t &base) const
+    {
+        const intsort_segment_desc e = d[s];
+        m = (uint32_t)e.n;
+        base = 0;
+        kin = static_cast<const K *>(e.keys_in);
+        kout = static_cast<K *>(e.keys_out);
+        vi = nullptr;
+        vo = nullptr;
+    }
+};
+
+template <class Src>
+struct LdsSortArgs {
+    Src src;
     const uint32_t *list;        // segment ids of this size class
     const uint32_t *list_count;  // device count of listed segments
 };
 
-template <typename K, bool PAIRS, int NT, int IPT>
-__global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<K> a)
+template <typename K, bool PAIRS, int NT, int IPT, class Src>
+__global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
 {
     constexpr int WAVES = NT / WAVE;
     constexpr int TILE = NT * IPT;
@@ -49,8 +84,12 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<K> a)
 
     if (blockIdx.x >= *a.list_count) return;
     const uint32_t seg = a.list[blockIdx.x];
-    const uint64_t start = a.offsets[seg];
-    const uint32_t m = (uint32_t)(a.offsets[seg + 1] - start);   // <= TILE by classification
+    const K *kin;
+    K *kout;
+    const uint32_t *vin;
+    uint32_t *vout;
+    uint32_t m, base_unused;
+    a.src.template seg<K>(seg, kin, kout, vin, vout, m, base_unused);   // m <= TILE by classification
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     const uint32_t lofs = wave * (IPT * WAVE) + lane;
 
@@ -59,12 +98,12 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<K> a)
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
         const bool in = lofs + j * WAVE < m;
-        k[j] = in ? a.in[start + lofs + j * WAVE] : ~K(0);
-        if (PAIRS) v[j] = in ? a.vin[start + lofs + j * WAVE] : 0u;
+        k[j] = in ? kin[lofs + j * WAVE] : ~K(0);
+        if (PAIRS) v[j] = in ? vin[lofs + j * WAVE] : 0u;
     }
 
     // bits in which some key differs from the first one
-    const K ref = m > 0 ? a.in[start] : K(0);
+    const K ref = m > 0 ? kin[0] : K(0);
     K diff = 0;
 #pragma unroll
     for (int j = 0; j < IPT; j++)
@@ -142,8 +181,8 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<K> a)
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
         if (lofs + j * WAVE < m) {
-            a.out[start + lofs + j * WAVE] = k[j];
-            if (PAIRS) a.vout[start + lofs + j * WAVE] = v[j];
+            kout[lofs + j * WAVE] = k[j];
+            if (PAIRS) vout[lofs + j * WAVE] = v[j];
         }
     }
 }

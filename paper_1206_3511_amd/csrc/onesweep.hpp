@@ -85,6 +85,10 @@ struct TileInfo {
     uint32_t first_tile;  // id of the first tile of the tile's segment
     uint32_t base;        // index of the segment's first key
     const uint32_t *excl; // exclusive digit offsets inside the segment
+    const void *in;       // the three key buffers the indices refer to
+    void *out;
+    void *tmp;
+    uint32_t limit;       // every store index stays below this
 };
 
 // one array of n keys in tiles of TILE keys
@@ -103,6 +107,7 @@ struct PlainTiles {
         return true;
     }
     __device__ bool missing_is_error() const { return true; }
+    __device__ uint32_t listed() const { return num_tiles; }
 };
 
 // tiles of many segments, listed on the device; the tiles of one segment
@@ -134,6 +139,44 @@ struct SegTiles {
         return true;
     }
     __device__ bool missing_is_error() const { return false; }
+    __device__ uint32_t listed() const { return *num_tiles; }
+};
+
+// key buffers of one segment of a batch of separate arrays
+struct SegBuf {
+    const void *in;
+    void *out;
+    void *tmp;
+    uint64_t n;
+};
+
+// tiles of a batch of separate arrays: indices are local to each array and
+// every array brings its own input, output and scratch buffers
+struct DescTiles {
+    const TileDesc *desc;
+    const uint32_t *num_tiles;
+    const uint32_t *seg_excl;
+    uint32_t radix;
+    const SegBuf *bufs;       // [slot]
+    template <int TILE>
+    __device__ __forceinline__ bool get(uint32_t t, TileInfo &ti) const
+    {
+        if (t >= *num_tiles) return false;
+        const TileDesc d = desc[t];
+        const SegBuf b = bufs[d.slot];
+        ti.start = d.start;
+        ti.count = d.count;
+        ti.first_tile = d.first_tile;
+        ti.base = d.base;
+        ti.excl = seg_excl + (uint64_t)d.slot * radix;
+        ti.in = b.in;
+        ti.out = b.out;
+        ti.tmp = b.tmp;
+        ti.limit = (uint32_t)b.n;
+        return true;
+    }
+    __device__ bool missing_is_error() const { return false; }
+    __device__ uint32_t listed() const { return *num_tiles; }
 };
 
 // ---------------------------------------------------------------- ranking
@@ -322,8 +365,6 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
 
     if (a.plan[0] == 0) return;   // pass skipped: the same for every workgroup
     const uint32_t srcc = a.plan[1], dstc = a.plan[2], ord = a.plan[3];
-    const K *src = srcc == BUF_IN ? a.in : (srcc == BUF_OUT ? a.out : a.tmp);
-    K *dst = dstc == BUF_OUT ? a.out : a.tmp;
     const uint32_t *vsrc = nullptr;
     uint32_t *vdst = nullptr;
     if (PAIRS) {
@@ -340,14 +381,19 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
     const uint32_t wave = tid / WAVE;
-    const uint32_t n = a.n;
 
-    for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
-    for (uint32_t i = tid; i < (uint32_t)(WAVES * BM); i += NT) s_bits[i] = 0;
+    // a grid sized for the most tiles possible: workgroups beyond the listed
+    // tiles leave before the shared counter, so exactly the listed ids are
+    // handed out (in the order workgroups reach the counter)
+    if (blockIdx.x >= tl.listed()) return;
     if (tid == 0) s_tile = atomicAdd(&a.counters[CTR_TILE + a.pass], 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
     TileInfo ti;
+    ti.in = a.in;
+    ti.out = a.out;
+    ti.tmp = a.tmp;
+    ti.limit = a.n;
     if (tile >= a.tile_capacity || !tl.template get<TILE>(tile, ti)) {
         // past the listed tiles (a grid sized for the most tiles possible),
         // or counters that were not reset: never index past the arrays
@@ -355,6 +401,12 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
             atomicOr(&a.counters[CTR_ERROR], DEVERR_BAD_TILE);
         return;
     }
+    for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
+    for (uint32_t i = tid; i < (uint32_t)(WAVES * BM); i += NT) s_bits[i] = 0;
+    __syncthreads();
+    const K *src = static_cast<const K *>(srcc == BUF_IN ? ti.in : (srcc == BUF_OUT ? ti.out : ti.tmp));
+    K *dst = static_cast<K *>(dstc == BUF_OUT ? ti.out : ti.tmp);
+    const uint32_t n = ti.limit;
     const uint32_t valid = ti.count;
     const bool first = tile == ti.first_tile;
 

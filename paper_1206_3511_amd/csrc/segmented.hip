@@ -57,15 +57,18 @@ struct SegWs {
     uint32_t *status1;
     uint32_t tile_cap;
     uint32_t slot_cap;
+    SegBuf *bufs;             // [slot_cap] separate arrays only, else null
+    void *tmp;                // scratch keys of the large segments
 };
 
 // One thread per segment: classify by size; a large segment reserves a run
-// of consecutive tile ids and writes their descriptors.  Thread 0 also writes
-// the plan of the digit passes (all of them run; the last lands in the
-// output buffer).
-template <typename K>
-__global__ __launch_bounds__(256) void k_seg_classify(const uint64_t *__restrict__ offsets, uint64_t num_segments,
-                                                      SegWs w, uint32_t passes, uint32_t in_place)
+// of consecutive tile ids and writes their descriptors (and, for separate
+// arrays, its buffers and a slice of the scratch buffer).  Thread 0 also
+// writes the plan of the digit passes: all of them run, alternating between
+// the scratch and the output buffer so that the last (an odd pass: there are
+// 4 or 8) lands in the output.
+template <typename K, class Src>
+__global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segments, SegWs w, uint32_t passes)
 {
     using CL = SegClasses<K>;
     constexpr uint32_t TILE = PassCfg<K, 8>::TILE;
@@ -74,26 +77,40 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint64_t *__restrict
         uint32_t prev = BUF_IN;
         for (uint32_t q = 0; q < passes; q++) {
             uint32_t *pw = w.plan + q * PLAN_WORDS;
-            const uint32_t dst = in_place ? ((q % 2 == 0) ? BUF_TMP : BUF_OUT)
-                                          : (((passes - 1 - q) % 2 == 0) ? BUF_OUT : BUF_TMP);
+            const uint32_t dst = (q % 2 == 0) ? BUF_TMP : BUF_OUT;
             pw[0] = 1; pw[1] = prev; pw[2] = dst; pw[3] = q;
             prev = dst;
         }
     }
-    if (s >= num_segments) return;
-    const uint64_t lo = offsets[s], hi = offsets[s + 1];
-    const uint32_t m = hi > lo ? (uint32_t)(hi - lo) : 0u;
-    int cls;
-    if (m <= CL::CAP0) cls = 0;
-    else if (m <= CL::CAP1) cls = 1;
-    else if (m <= CL::CAP2) cls = 2;
-    else if (m <= CL::CAP3) cls = 3;
-    else cls = 4;
-    if (cls < 4) {
-        const uint32_t at = atomicAdd(&w.counters[CTR_SEG_CLASS + cls], 1u);
-        if (at < w.list_stride) w.lists[cls * w.list_stride + at] = (uint32_t)s;
-        return;
+    const K *kin = nullptr;
+    K *kout = nullptr;
+    const uint32_t *vin;
+    uint32_t *vout;
+    uint32_t m = 0, lo = 0;
+    int cls = -1;
+    if (s < num_segments) {
+        src.template seg<K>(s, kin, kout, vin, vout, m, lo);
+        if (m <= CL::CAP0) cls = 0;
+        else if (m <= CL::CAP1) cls = 1;
+        else if (m <= CL::CAP2) cls = 2;
+        else if (m <= CL::CAP3) cls = 3;
+        else cls = 4;
     }
+    // one atomic per wave and class: the wave's lanes of a class take
+    // consecutive list entries
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const uint64_t mine = ballot(cls == c);
+        if (mine == 0) continue;
+        uint32_t base = 0;
+        if (mbcnt(mine) == 0 && cls == c) base = atomicAdd(&w.counters[CTR_SEG_CLASS + c], popc64(mine));
+        base = __shfl(base, __builtin_ctzll(mine), WAVE);
+        if (cls == c) {
+            const uint32_t at = base + mbcnt(mine);
+            if (at < w.list_stride) w.lists[c * w.list_stride + at] = (uint32_t)s;
+        }
+    }
+    if (cls != 4) return;
     const uint32_t nt = (m + TILE - 1) / TILE;
     const uint32_t slot = atomicAdd(&w.counters[CTR_SEG_SLOTS], 1u);
     const uint32_t first = atomicAdd(&w.counters[CTR_SEG_TILES], nt);
@@ -103,13 +120,22 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint64_t *__restrict
     }
     w.slot_first[slot] = first;
     w.slot_ntiles[slot] = nt;
+    if (w.bufs) {
+        const uint32_t toff = atomicAdd(&w.counters[CTR_SEG_TMP], m);
+        SegBuf b;
+        b.in = kin;
+        b.out = kout;
+        b.tmp = static_cast<K *>(w.tmp) + toff;
+        b.n = m;
+        w.bufs[slot] = b;
+    }
     for (uint32_t t = 0; t < nt; t++) {
         TileDesc d;
         d.slot = slot;
         d.first_tile = first;
-        d.start = (uint32_t)lo + t * TILE;
+        d.start = lo + t * TILE;
         d.count = min(TILE, m - t * TILE);
-        d.base = (uint32_t)lo;
+        d.base = lo;
         d.pad[0] = d.pad[1] = d.pad[2] = 0;
         w.tiles[first + t] = d;
     }
@@ -137,12 +163,13 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
     const uint32_t t = blockIdx.x;
     if (t >= w.counters[CTR_SEG_TILES]) return;
     const TileDesc d = w.tiles[t];
+    const K *kp = w.bufs ? static_cast<const K *>(w.bufs[d.slot].in) : keys;
     for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS) s_h[i] = 0;
     for (uint32_t i = threadIdx.x; i < 256u; i += SEG_HIST_THREADS) w.status0[(uint64_t)t * 256 + i] = 0;
     if (threadIdx.x == 0) w.status0[(uint64_t)w.tile_cap * 256 + t] = 0;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < d.count; i += SEG_HIST_THREADS) {
-        const K k = keys[d.start + i];
+        const K k = kp[d.start + i];
 #pragma unroll
         for (int p = 0; p < PASSES; p++) seg_hist_add<256>(s_h + p * 256, digit_at<K>(k, 8u * p, 0xffu));
     }
@@ -179,7 +206,8 @@ static SegLayout seg_layout_typed(uint64_t n, uint64_t S)
     constexpr uint32_t TILE = PassCfg<K, 8>::TILE;
     constexpr int PASSES = (int)sizeof(K);
     SegLayout L{};
-    L.slot_cap = (uint32_t)std::min<uint64_t>(S, n / (CL::LDS_MAX + 1) + 1);
+    // no more segments than this can be longer than the on-chip classes hold
+    L.slot_cap = (uint32_t)std::min<uint64_t>(S, n / (CL::LDS_MAX + 1));
     L.tile_cap = (uint32_t)((n + TILE - 1) / TILE + L.slot_cap);
     L.list_stride = (uint32_t)S;
     size_t off = 0;
@@ -190,6 +218,7 @@ static SegLayout seg_layout_typed(uint64_t n, uint64_t S)
     L.slot_first = take((size_t)L.slot_cap * 4);
     L.slot_ntiles = take((size_t)L.slot_cap * 4);
     L.tiles = take((size_t)L.tile_cap * sizeof(TileDesc));
+    L.bufs = take((size_t)L.slot_cap * sizeof(SegBuf));
     L.tile_hist = take((size_t)L.tile_cap * PASSES * 256 * 4);
     L.seg_excl = take((size_t)PASSES * L.slot_cap * 256 * 4);
     L.status0 = take((size_t)L.tile_cap * 257 * 4);
@@ -207,15 +236,20 @@ SegLayout segmented_layout(int key_bytes, bool pairs, uint64_t n, uint64_t num_s
     return pairs ? seg_layout_typed<uint64_t, true>(n, num_segments) : seg_layout_typed<uint64_t, false>(n, num_segments);
 }
 
-template <typename K, bool PAIRS, int NT, int IPT>
-static void launch_lds_class(const LdsSortArgs<K> &la, uint32_t grid, hipStream_t s)
+template <typename K, bool PAIRS, int NT, int IPT, class Src>
+static void launch_lds_class(const LdsSortArgs<Src> &la, uint32_t grid, hipStream_t s)
 {
     if (grid == 0) return;
-    hipLaunchKernelGGL((k_lds_sort<K, PAIRS, NT, IPT>), dim3(grid), dim3(NT), 0, s, la);
+    hipLaunchKernelGGL((k_lds_sort<K, PAIRS, NT, IPT, Src>), dim3(grid), dim3(NT), 0, s, la);
 }
 
-template <typename K, bool PAIRS>
-static hipError_t seg_run_typed(const SegCall &c, hipStream_t s)
+static void set_bufs(SegTiles &, const SegBuf *) {}
+static void set_bufs(DescTiles &t, const SegBuf *b) { t.bufs = b; }
+
+// the whole segmented sort for one key type; Src says where segments live,
+// Tiles how the digit passes of the large ones find their buffers
+template <typename K, bool PAIRS, class Src, class TilesT>
+static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate, hipStream_t s)
 {
     using CL = SegClasses<K>;
     using PC = PassCfg<K, 8>;
@@ -237,22 +271,19 @@ static hipError_t seg_run_typed(const SegCall &c, hipStream_t s)
     w.status1 = reinterpret_cast<uint32_t *>(ws + L.status1);
     w.tile_cap = L.tile_cap;
     w.slot_cap = L.slot_cap;
-    const bool in_place = c.keys_in == c.keys_out;
+    w.bufs = separate ? reinterpret_cast<SegBuf *>(ws + L.bufs) : nullptr;
+    w.tmp = ws + L.tmp_keys;
 
     if (tm) tm->start(s);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, w.counters, (uint64_t)CTR_WORDS, 0u);
     const uint32_t cgrid = (uint32_t)((c.num_segments + 255) / 256);
-    hipLaunchKernelGGL((k_seg_classify<K>), dim3(cgrid), dim3(256), 0, s, c.offsets, c.num_segments, w,
-                       (uint32_t)PASSES, in_place ? 1u : 0u);
+    hipLaunchKernelGGL((k_seg_classify<K, Src>), dim3(cgrid), dim3(256), 0, s, src, c.num_segments, w,
+                       (uint32_t)PASSES);
     if (tm) tm->mark(INTSORT_KERNEL_PLAN, 0, s);
 
     // the four on-chip classes
-    LdsSortArgs<K> la{};
-    la.in = static_cast<const K *>(c.keys_in);
-    la.out = static_cast<K *>(c.keys_out);
-    la.vin = c.vals_in;
-    la.vout = c.vals_out;
-    la.offsets = c.offsets;
+    LdsSortArgs<Src> la{};
+    la.src = src;
     const uint64_t S = c.num_segments;
     auto grid_for = [&](uint32_t lo_exclusive) {
         // at most this many segments can be longer than lo_exclusive
@@ -276,6 +307,7 @@ static hipError_t seg_run_typed(const SegCall &c, hipStream_t s)
     if (tm) tm->mark(INTSORT_KERNEL_SEGMENT_SORT, 0, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (L.slot_cap == 0) return hipSuccess;   // no segment can be large
 
     // the large segments: digit counts per tile, offsets per segment, passes
     hipLaunchKernelGGL((k_seg_tile_hist<K>), dim3(L.tile_cap), dim3(SEG_HIST_THREADS), 0, s,
@@ -300,8 +332,13 @@ static hipError_t seg_run_typed(const SegCall &c, hipStream_t s)
         a.plan = w.plan + p * PLAN_WORDS;
         a.pass = (uint32_t)p;
         const RadixDigit dg{(uint32_t)(8 * p), 0xffu};
-        const SegTiles tl{w.tiles, w.counters + CTR_SEG_TILES, w.seg_excl + (uint64_t)p * L.slot_cap * 256, 256u};
-        hipLaunchKernelGGL((k_onesweep<K, 8, PAIRS, RadixDigit, SegTiles>), dim3(L.tile_cap), dim3(PC::NT), 0, s,
+        TilesT tl{};
+        tl.desc = w.tiles;
+        tl.num_tiles = w.counters + CTR_SEG_TILES;
+        tl.seg_excl = w.seg_excl + (uint64_t)p * L.slot_cap * 256;
+        tl.radix = 256u;
+        set_bufs(tl, w.bufs);
+        hipLaunchKernelGGL((k_onesweep<K, 8, PAIRS, RadixDigit, TilesT>), dim3(L.tile_cap), dim3(PC::NT), 0, s,
                            a, dg, tl);
         if (tm) tm->mark(INTSORT_KERNEL_PASS, (uint32_t)p, s);
     }
@@ -311,8 +348,18 @@ static hipError_t seg_run_typed(const SegCall &c, hipStream_t s)
 hipError_t segmented_sort_run(const SegCall &c, hipStream_t s)
 {
     if (c.opts.digit_bits != 8) return hipErrorNotSupported;
-    if (c.key_bytes == 4) return c.pairs ? seg_run_typed<uint32_t, true>(c, s) : seg_run_typed<uint32_t, false>(c, s);
-    return c.pairs ? seg_run_typed<uint64_t, true>(c, s) : seg_run_typed<uint64_t, false>(c, s);
+    if (c.descs) {
+        if (c.pairs) return hipErrorNotSupported;
+        const DescSrc src{c.descs};
+        if (c.key_bytes == 4) return seg_run_typed<uint32_t, false, DescSrc, DescTiles>(c, src, true, s);
+        return seg_run_typed<uint64_t, false, DescSrc, DescTiles>(c, src, true, s);
+    }
+    const PackedSrc src{c.keys_in, c.keys_out, c.vals_in, c.vals_out, c.offsets};
+    if (c.key_bytes == 4)
+        return c.pairs ? seg_run_typed<uint32_t, true, PackedSrc, SegTiles>(c, src, false, s)
+                       : seg_run_typed<uint32_t, false, PackedSrc, SegTiles>(c, src, false, s);
+    return c.pairs ? seg_run_typed<uint64_t, true, PackedSrc, SegTiles>(c, src, false, s)
+                   : seg_run_typed<uint64_t, false, PackedSrc, SegTiles>(c, src, false, s);
 }
 
 }  // namespace intsort

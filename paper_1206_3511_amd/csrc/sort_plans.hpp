@@ -14,7 +14,7 @@ constexpr uint32_t MAX_BUCKETS = 1u << 16;
 constexpr uint64_t MAX_SEGMENTS = 1ull << 24;
 
 struct SegLayout {
-    size_t counters, plan, lists, slot_first, slot_ntiles, tiles, tile_hist, seg_excl, status0, status1;
+    size_t counters, plan, lists, slot_first, slot_ntiles, tiles, bufs, tile_hist, seg_excl, status0, status1;
     size_t tmp_keys, tmp_vals, total;
     uint32_t slot_cap, tile_cap, list_stride;
 };
@@ -52,6 +52,7 @@ struct SegCall {
     uint64_t n;
     uint64_t num_segments;
     const uint64_t *offsets;
+    const intsort_segment_desc *descs;   // separate arrays instead of offsets, or null
     int key_bytes;
     bool pairs;
     intsort_options opts;

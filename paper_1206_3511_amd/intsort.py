@@ -35,7 +35,9 @@ EXPORTED = (
     "intsort_workspace_size", "intsort_sort_keys", "intsort_sort_pairs",
     "intsort_segmented_sort_keys", "intsort_segmented_sort_pairs", "intsort_digit_histogram",
     "intsort_minmax", "intsort_bucket_histogram", "intsort_read_device_error",
-    "intsort_timing_enable", "intsort_timing_read",
+    "intsort_timing_enable", "intsort_timing_read", "intsort_batched_sort_keys",
+    "intsort_server_create", "intsort_server_submit", "intsort_server_poll", "intsort_server_completed",
+    "intsort_server_drain", "intsort_server_destroy",
 )
 
 KERNEL_KINDS = ("init", "digit_histogram", "pass", "copy", "minmax", "bucket_histogram",
@@ -100,6 +102,15 @@ def lib():
         L.intsort_bucket_histogram.argtypes = [_vp, _i, _vp, _u64, _vp, ctypes.c_uint32, _vp, _vp]
         L.intsort_read_device_error.argtypes = [_vp, _vp, ctypes.c_size_t,
                                                 ctypes.POINTER(ctypes.c_uint32), _vp]
+        L.intsort_batched_sort_keys.argtypes = [_vp, _i, _vp, _u64, _u64, ctypes.POINTER(Options), _vp,
+                                                ctypes.c_size_t, _vp]
+        L.intsort_server_create.argtypes = [_vp, _u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_vp)]
+        L.intsort_server_submit.argtypes = [_vp, _i, _vp, _vp, _u64, ctypes.POINTER(_u64)]
+        L.intsort_server_poll.argtypes = [_vp, _u64, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]
+        L.intsort_server_completed.argtypes = [_vp, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double),
+                                               ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        L.intsort_server_drain.argtypes = [_vp]
+        L.intsort_server_destroy.argtypes = [_vp]
         L.intsort_timing_enable.argtypes = [_vp, _i]
         L.intsort_timing_read.argtypes = [_vp, ctypes.POINTER(KernelTime), ctypes.c_uint32,
                                           ctypes.POINTER(ctypes.c_uint32)]
@@ -271,6 +282,34 @@ def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Tensor
     return ok, ov
 
 
+def batched_sort(inputs: list, outputs: list | None = None, stream=None) -> list:
+    """Sort several separate device arrays (all 32-bit or all 64-bit) in one
+    set of launches; returns the output tensors."""
+    if not inputs:
+        return []
+    kt = _key_type(inputs[0])
+    outputs = [torch.empty_like(t) for t in inputs] if outputs is None else outputs
+    desc = torch.empty((len(inputs), 3), dtype=torch.int64)
+    for i, (a, b) in enumerate(zip(inputs, outputs)):
+        _dev_tensor(a, "input")
+        _dev_tensor(b, "output")
+        if _key_type(a) != kt or a.numel() != b.numel():
+            raise ValueError("all arrays must share the key type; outputs must match inputs")
+        desc[i, 0] = a.data_ptr()
+        desc[i, 1] = b.data_ptr()
+        desc[i, 2] = a.numel()
+    dev = inputs[0].device
+    d_desc = desc.to(dev)
+    total = int(sum(t.numel() for t in inputs))
+    ctx = context(dev.index)
+    o = make_options("radix")
+    ws = ctx.workspace(ctx.workspace_size(kt, False, total, len(inputs), o))
+    _check(lib().intsort_batched_sort_keys(ctx.handle, kt, d_desc.data_ptr(), len(inputs), total, ctypes.byref(o),
+                                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+           "intsort_batched_sort_keys")
+    return outputs
+
+
 def digit_histogram(keys: torch.Tensor, digit_bits: int = 8, stream=None) -> torch.Tensor:
     """counts[p, v]: keys whose digit p equals v, for every pass p."""
     _dev_tensor(keys, "keys")
@@ -314,3 +353,62 @@ def device_error(device: int = 0, stream=None) -> int:
     _check(lib().intsort_read_device_error(ctx.handle, ctx._ws.data_ptr(), ctx._ws.numel(), ctypes.byref(w),
                                            _stream_ptr(stream)), "intsort_read_device_error")
     return w.value
+
+
+class Server:
+    """Continuous-batching sort server (intsort_server_*).  Keeps every
+    submitted request's tensors alive until it completes."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 64 << 30, max_batch: int = 64, slots: int = 2):
+        torch.cuda.set_device(device)
+        self.handle = _vp()
+        _check(lib().intsort_server_create(context(device).handle, budget_bytes, max_batch, slots,
+                                           ctypes.byref(self.handle)), "intsort_server_create")
+        self._live: dict[int, tuple] = {}
+        self._buf_t = (_u64 * 4096)()
+        self._buf_l = (ctypes.c_double * 4096)()
+
+    def submit(self, keys: torch.Tensor, out: torch.Tensor) -> int:
+        _dev_tensor(keys, "keys")
+        _dev_tensor(out, "out")
+        t = _u64(0)
+        _check(lib().intsort_server_submit(self.handle, _key_type(keys), _ptr(keys), _ptr(out), keys.numel(),
+                                           ctypes.byref(t)), "intsort_server_submit")
+        self._live[t.value] = (keys, out)
+        return t.value
+
+    def completed(self) -> list[tuple[int, float]]:
+        """(ticket, latency seconds) of requests finished since the last call."""
+        res = []
+        while True:
+            cnt = ctypes.c_uint32(0)
+            _check(lib().intsort_server_completed(self.handle, self._buf_t, self._buf_l, 4096, ctypes.byref(cnt)),
+                   "intsort_server_completed")
+            for i in range(cnt.value):
+                res.append((int(self._buf_t[i]), float(self._buf_l[i])))
+                self._live.pop(int(self._buf_t[i]), None)
+            if cnt.value < 4096:
+                return res
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int(0)
+        lat = ctypes.c_double(0.0)
+        rc = lib().intsort_server_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(lat))
+        if rc not in (OK, ERR_NOT_READY):
+            raise IntsortError(rc, "intsort_server_poll")
+        return bool(done.value), lat.value
+
+    def drain(self):
+        _check(lib().intsort_server_drain(self.handle), "intsort_server_drain")
+
+    def close(self):
+        if self.handle:
+            _check(lib().intsort_server_destroy(self.handle), "intsort_server_destroy")
+            self.handle = _vp()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,93 @@
+"""GPU tests of the batched sort of separate arrays and of the
+continuous-batching server: every result equals the oracle's, and equals
+the same request sorted alone (alone-vs-mix, tolerance 0)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1206_3511_amd import intsort as I
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 100, 256, 257, 2048, 2049, 8192, 8193, 16384, 16385, 50_000, 200_003, 0]
+
+
+def _requests(seed, count, sizes=None):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        n = sizes[i % len(sizes)] if sizes is not None else int(rng.integers(1, 300_000))
+        dist = int(rng.integers(0, 7))
+        keys = workloads.config2_keys(dist, n, 5000 + seed * 1000 + i)
+        if rng.integers(0, 2):
+            keys = (keys.astype(np.uint64) << np.uint64(int(rng.integers(0, 33)))) | keys.astype(np.uint64)
+        reqs.append(keys)
+    return reqs
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_batched_sort_separate_arrays(dtype):
+    arrays = [a.astype(dtype) for a in _requests(1, len(SIZES), SIZES)]
+    ins = [dev(a) for a in arrays if a.size]
+    outs = I.batched_sort(ins)
+    for a, o in zip([a for a in arrays if a.size], outs):
+        np.testing.assert_array_equal(host(o), oracle.radix_lsd(a).keys)
+    # in place
+    ins2 = [dev(a) for a in arrays if a.size]
+    I.batched_sort(ins2, outputs=ins2)
+    for a, o in zip([a for a in arrays if a.size], ins2):
+        np.testing.assert_array_equal(host(o), np.sort(a))
+
+
+def _serve(reqs, budget, max_batch, slots, spacing_s=0.0):
+    srv = I.Server(0, budget_bytes=budget, max_batch=max_batch, slots=slots)
+    ins = [dev(a) for a in reqs]
+    outs = [torch.empty_like(t) for t in ins]
+    torch.cuda.synchronize()
+    tickets = []
+    for a, b in zip(ins, outs):
+        tickets.append(srv.submit(a, b))
+        if spacing_s:
+            time.sleep(spacing_s)
+    srv.drain()
+    done = dict(srv.completed())
+    assert set(done) == set(tickets)
+    assert all(v >= 0 for v in done.values())
+    res = [host(o) for o in outs]
+    srv.close()
+    return res
+
+
+def test_server_alone_vs_mix_and_oracle():
+    reqs = _requests(2, 60)
+    mixed = _serve(reqs, budget=16 << 30, max_batch=64, slots=2, spacing_s=0.0005)
+    for a, got in zip(reqs, mixed):
+        alone = host(I.sort(dev(a)))
+        assert got.tobytes() == alone.tobytes()           # alone == in the mix, exactly
+        np.testing.assert_array_equal(got, oracle.radix_lsd(a).keys)
+
+
+def test_server_budget_queueing_and_plain_path():
+    reqs = _requests(3, 24, sizes=[100_000, 30_000, 5000])
+    # room for about two requests at a time: the rest wait and are admitted
+    # as memory frees up
+    tight = _serve(reqs, budget=4 << 20, max_batch=16, slots=2)
+    plain = _serve(reqs, budget=64 << 30, max_batch=1, slots=1)
+    for a, t, p in zip(reqs, tight, plain):
+        ref = oracle.radix_lsd(a).keys
+        np.testing.assert_array_equal(t, ref)
+        np.testing.assert_array_equal(p, ref)
+
+
+def test_server_rejects_over_budget():
+    srv = I.Server(0, budget_bytes=1 << 20, max_batch=4, slots=1)
+    a = torch.zeros(1 << 20, dtype=torch.uint32, device="cuda:0")
+    with pytest.raises(I.IntsortError) as e:
+        srv.submit(a, torch.empty_like(a))
+    assert e.value.status == I.ERR_OVER_BUDGET
+    srv.close()

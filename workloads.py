@@ -202,3 +202,104 @@ def checksum(a: np.ndarray) -> int:
     with np.errstate(over="ignore"):
         folded = mix64(words ^ (idx * GAMMA))
     return mix64_int(h ^ int(np.bitwise_xor.reduce(folded)) if folded.size else h)
+
+
+# ----------------------------------------------------------------------------
+# Device-side generation (torch), for workloads too large to feed over PCIe.
+# The same counter-based SplitMix64 on int64 tensors: products wrap modulo
+# 2^64 and right shifts are made logical with a mask.  Outputs are int64
+# tensors holding the 64-bit patterns.
+
+def _lsr(x, s: int):
+    import torch
+    return (x >> s) & ((1 << (64 - s)) - 1)
+
+
+def _to_i64(u: int) -> int:
+    return u - (1 << 64) if u >= (1 << 63) else u
+
+
+def device_u64_stream(seed: int, stream: int, n: int, device, start: int = 0):
+    """Elements start .. start+n-1 of stream (seed, stream), as int64 bit
+    patterns on `device` (equal to u64_stream's values)."""
+    import torch
+    base = torch.tensor(_to_i64(stream_base(seed, stream)), dtype=torch.int64, device=device)
+    g = torch.tensor(_to_i64(int(GAMMA)), dtype=torch.int64, device=device)
+    m1 = torch.tensor(_to_i64(int(_M1)), dtype=torch.int64, device=device)
+    m2 = torch.tensor(_to_i64(int(_M2)), dtype=torch.int64, device=device)
+    z = base + torch.arange(start + 1, start + n + 1, dtype=torch.int64, device=device) * g
+    z = (z ^ _lsr(z, 30)) * m1
+    z = (z ^ _lsr(z, 27)) * m2
+    return z ^ _lsr(z, 31)
+
+
+def device_keys(dist: int, n: int, seed: int, width: int, device):
+    """n keys of one of the seven distributions made on the device, as a
+    torch uint32 (width 4) or uint64 (width 8) tensor.  For 64-bit keys the
+    fields are taken from the top of the 64-bit random value: uniform r,
+    small r >> 54, mid r >> 48; sorted/reverse sort the uniform keys as
+    unsigned; 'swaps' exchanges floor(n/100) disjoint position pairs (drawn
+    from stream 1) of the sorted keys; 'gaussian' puts 16 clusters of width
+    2^20 (32-bit) or 2^52 (64-bit) at uniform means."""
+    import math
+    import torch
+    r = device_u64_stream(seed, 0, n, device)
+    if width == 4:
+        top = _lsr(r, 32)
+        keys = {0: top, 1: _lsr(r, 54), 2: _lsr(r, 48)}.get(dist)
+        full_bits = 32
+    else:
+        keys = {0: r, 1: _lsr(r, 54), 2: _lsr(r, 48)}.get(dist)
+        full_bits = 64
+    if dist in (3, 4, 5):
+        u = r if width == 8 else _lsr(r, 32)
+        flip = (-(1 << 63)) if width == 8 else 0
+        keys = torch.sort(u ^ flip).values ^ flip
+        if dist == 4:
+            keys = keys.flip(0)
+        elif dist == 5 and n >= 2:
+            m = n // 100
+            if m:
+                pos = torch.argsort(_lsr(device_u64_stream(seed, 1, n, device), 1))[: 2 * m]
+                i, j = pos[0::2], pos[1::2]
+                ki, kj = keys[i].clone(), keys[j].clone()
+                keys[i], keys[j] = kj, ki
+    if dist == 6:
+        mu = _lsr(device_u64_stream(seed, 2, 16, device), 64 - full_bits).to(torch.float64)
+        if width == 8:
+            mu = torch.where(mu < 0, mu + 2.0 ** 64, mu)
+        c = _lsr(r, 60)
+        u1 = (_lsr(device_u64_stream(seed, 3, n, device), 11).to(torch.float64) + 1.0) / float(1 << 53)
+        u2 = _lsr(device_u64_stream(seed, 4, n, device), 11).to(torch.float64) / float(1 << 53)
+        z = torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * math.pi * u2)
+        x = mu[c] + float(1 << (20 if width == 4 else 52)) * z
+        x = torch.where(x >= 0, torch.floor(x + 0.5), torch.ceil(x - 0.5))
+        hi = float((1 << 32) - 1) if width == 4 else float(2 ** 64 - 2048)
+        x = torch.clamp(x, 0.0, hi)
+        if width == 4:
+            keys = x.to(torch.int64)
+        else:
+            big = x >= 2.0 ** 63
+            keys = torch.where(big, (x - 2.0 ** 63).to(torch.int64) ^ (-(1 << 63)), x.to(torch.int64))
+    if width == 4:
+        return keys.to(torch.int32).view(torch.uint32) if keys.dtype == torch.int64 else keys
+    return keys.view(torch.uint64)
+
+
+def serving_trace(rate: float = 2000.0, seconds: float = 60.0, seed: int = 5, lo: int = 1024,
+                  base: int = 65536):
+    """Poisson arrivals (exponential gaps) over `seconds`, each request
+    (arrival time, key width 4 or 8 by coin flip, n = floor(lo * base^u),
+    distribution index)."""
+    count = int(rate * seconds * 1.5) + 16
+    g = (u64_stream(seed, 0, count) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    gaps = -np.log1p(-g) / rate
+    t = np.cumsum(gaps)
+    keep = t < seconds
+    t = t[keep]
+    k = t.size
+    w = np.where((u64_stream(seed, 1, k) >> np.uint64(63)) == 1, 8, 4)
+    u = (u64_stream(seed, 2, k) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    n = np.floor(lo * np.power(float(base), u)).astype(np.int64)
+    d = ((u64_stream(seed, 3, k) >> np.uint64(32)) * np.uint64(7) >> np.uint64(32)).astype(np.int64)
+    return t, w, n, d
