@@ -208,7 +208,14 @@ def run_batched(name, p, args):
     out = torch.empty_like(k)
     offs = torch.from_numpy(offsets.view(np.int64)).to("cuda:0")
     ctx = I.context(0)
-    fn = lambda: I.segmented_sort(k, offs, out_keys=out)  # noqa: E731
+    from paper_1206_3511_amd import autotune
+
+    choice = autotune.tuned_options("segmented", 4, N)
+    tuned_now = not choice
+    if tuned_now:
+        print(f"bench[{name}]: autotuning the LDS cutoff", file=sys.stderr, flush=True)
+        choice = autotune.tune_segmented(k, offs)
+    fn = lambda: I.segmented_sort(k, offs, out_keys=out, **choice)  # noqa: E731
     steps = max(1, args.steps // 4)
     ms = _timed(fn, steps, 1)
     value = N / (ms * 1e-3) / 1e9
@@ -224,7 +231,8 @@ def run_batched(name, p, args):
     roof = _roofline("k_onesweep<SegTiles> (one digit pass of the large arrays)", 2 * N * 4,
                      avg.get("pass", float("nan")), {"kernel_avg_ms": {kk: round(x, 5) for kk, x in avg.items()}})
     return _line("Gkeys/s (batched segmented sort of 10,000 uint32 arrays)", value, "Gkeys/s", ms, steps, 1, "u32",
-                 {"workload": name, "arrays": len(offsets) - 1, "keys": int(N), "sizes": "log-uniform [16, 2^20)"},
+                 {"workload": name, "arrays": len(offsets) - 1, "keys": int(N), "sizes": "log-uniform [16, 2^20)",
+                  "tuned": choice, "tuned_in_this_run": tuned_now},
                  roof, None, per_array_loop={"value": round(N / (ms_loop * 1e-3) / 1e9, 3), "ms": round(ms_loop, 3)},
                  speedup_vs_per_array_loop=round(ms_loop / ms, 2))
 

@@ -78,9 +78,11 @@ typedef enum intsort_algo {
  *   num_buckets  bucket sort: number of buckets B, 1..65536 (default 1024
  *                for u32, 65536 for u64).  The bucket of key k is
  *                floor((k - min) * B / (max - min + 1)), exact.
- *   lds_cutoff   bucket/segmented: segments of at most this many keys are
- *                sorted by one workgroup entirely in LDS (default: the
- *                largest size one workgroup holds).
+ *   lds_cutoff   bucket/segmented/batched: segments of at most this many
+ *                keys are sorted by one workgroup entirely in LDS, longer
+ *                ones by all workgroups together (0 or more than one
+ *                workgroup holds = the largest size one workgroup holds:
+ *                16384 32-bit or 8192 64-bit keys).
  *   max_passes   radix: stop after this many digit passes (0 = all).  With a
  *                value p the output is the input stably sorted on its low
  *                p*r bits; this exposes the intermediate arrays of

@@ -59,6 +59,7 @@ struct SegWs {
     uint32_t slot_cap;
     SegBuf *bufs;             // [slot_cap] separate arrays only, else null
     void *tmp;                // scratch keys of the large segments
+    uint32_t lds_cutoff;      // longer segments take the multi-workgroup path
 };
 
 // One thread per segment: classify by size; a large segment reserves a run
@@ -90,7 +91,8 @@ __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segm
     int cls = -1;
     if (s < num_segments) {
         src.template seg<K>(s, kin, kout, vin, vout, m, lo);
-        if (m <= CL::CAP0) cls = 0;
+        if (m > w.lds_cutoff) cls = 4;
+        else if (m <= CL::CAP0) cls = 0;
         else if (m <= CL::CAP1) cls = 1;
         else if (m <= CL::CAP2) cls = 2;
         else if (m <= CL::CAP3) cls = 3;
@@ -199,22 +201,29 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegWs w)
 
 // ------------------------------------------------------------------ host
 
-template <typename K, bool PAIRS>
-static SegLayout seg_layout_typed(uint64_t n, uint64_t S)
+template <typename K>
+static uint32_t seg_cutoff(uint32_t requested)
 {
     using CL = SegClasses<K>;
+    return (requested == 0 || requested > CL::LDS_MAX) ? CL::LDS_MAX : requested;
+}
+
+template <typename K, bool PAIRS>
+static SegLayout seg_layout_typed(uint64_t n, uint64_t S, uint32_t cutoff_req)
+{
     constexpr uint32_t TILE = PassCfg<K, 8>::TILE;
     constexpr int PASSES = (int)sizeof(K);
     SegLayout L{};
-    // no more segments than this can be longer than the on-chip classes hold
-    L.slot_cap = (uint32_t)std::min<uint64_t>(S, n / (CL::LDS_MAX + 1));
+    L.lds_cutoff = seg_cutoff<K>(cutoff_req);
+    // no more segments than this can be longer than the cutoff
+    L.slot_cap = (uint32_t)std::min<uint64_t>(S, n / ((uint64_t)L.lds_cutoff + 1));
     L.tile_cap = (uint32_t)((n + TILE - 1) / TILE + L.slot_cap);
     L.list_stride = (uint32_t)S;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
     L.counters = take((size_t)CTR_WORDS * 4);
     L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
-    L.lists = take((size_t)CL::NCLASS * S * 4);
+    L.lists = take((size_t)SegClasses<K>::NCLASS * S * 4);
     L.slot_first = take((size_t)L.slot_cap * 4);
     L.slot_ntiles = take((size_t)L.slot_cap * 4);
     L.tiles = take((size_t)L.tile_cap * sizeof(TileDesc));
@@ -229,11 +238,13 @@ static SegLayout seg_layout_typed(uint64_t n, uint64_t S)
     return L;
 }
 
-SegLayout segmented_layout(int key_bytes, bool pairs, uint64_t n, uint64_t num_segments, const intsort_options &)
+SegLayout segmented_layout(int key_bytes, bool pairs, uint64_t n, uint64_t num_segments, const intsort_options &o)
 {
-    if (key_bytes == 4) return pairs ? seg_layout_typed<uint32_t, true>(n, num_segments)
-                                     : seg_layout_typed<uint32_t, false>(n, num_segments);
-    return pairs ? seg_layout_typed<uint64_t, true>(n, num_segments) : seg_layout_typed<uint64_t, false>(n, num_segments);
+    const uint32_t c = o.lds_cutoff;
+    if (key_bytes == 4) return pairs ? seg_layout_typed<uint32_t, true>(n, num_segments, c)
+                                     : seg_layout_typed<uint32_t, false>(n, num_segments, c);
+    return pairs ? seg_layout_typed<uint64_t, true>(n, num_segments, c)
+                 : seg_layout_typed<uint64_t, false>(n, num_segments, c);
 }
 
 template <typename K, bool PAIRS, int NT, int IPT, class Src>
@@ -273,6 +284,7 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     w.slot_cap = L.slot_cap;
     w.bufs = separate ? reinterpret_cast<SegBuf *>(ws + L.bufs) : nullptr;
     w.tmp = ws + L.tmp_keys;
+    w.lds_cutoff = L.lds_cutoff;
 
     if (tm) tm->start(s);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, w.counters, (uint64_t)CTR_WORDS, 0u);
@@ -286,7 +298,9 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     la.src = src;
     const uint64_t S = c.num_segments;
     auto grid_for = [&](uint32_t lo_exclusive) {
-        // at most this many segments can be longer than lo_exclusive
+        // at most this many segments can be longer than lo_exclusive; none
+        // longer than the cutoff reaches an on-chip class
+        if (lo_exclusive >= L.lds_cutoff) return 0u;
         const uint64_t by_n = c.n / (uint64_t)(lo_exclusive + 1);
         return (uint32_t)std::min<uint64_t>(S, lo_exclusive == 0 ? S : by_n);
     };

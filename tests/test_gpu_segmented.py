@@ -20,11 +20,11 @@ def _offsets(sizes):
     return np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
 
 
-def _run(keys, offsets, vals=None):
+def _run(keys, offsets, vals=None, **opt):
     offs = torch.from_numpy(offsets.view(np.int64)).to("cuda:0")
     if vals is None:
-        return host(I.segmented_sort(dev(keys), offs)), None
-    ok, ov = I.segmented_sort(dev(keys), offs, dev(vals))
+        return host(I.segmented_sort(dev(keys), offs, **opt)), None
+    ok, ov = I.segmented_sort(dev(keys), offs, dev(vals), **opt)
     return host(ok), host(ov)
 
 
@@ -40,6 +40,21 @@ def test_segment_class_boundaries(dtype, pairs):
     np.testing.assert_array_equal(ok, rk)
     if pairs:
         np.testing.assert_array_equal(ov, rv)
+
+
+@pytest.mark.parametrize("cutoff", [1, 256, 2048, 8192, 0])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_lds_cutoff_does_not_change_result(dtype, cutoff):
+    """Every segment size class boundary moved by the cutoff option (longer
+    segments take the multi-workgroup path): same bytes as the oracle."""
+    offsets = _offsets(BOUNDARY_SIZES)
+    n = int(offsets[-1])
+    keys = rand_keys(np.random.default_rng(6), n, dtype)
+    vals = np.arange(n, dtype=np.uint32)
+    ok, ov = _run(keys, offsets, vals, lds_cutoff=cutoff)
+    rk, rv = oracle.segmented(keys, offsets, vals)
+    np.testing.assert_array_equal(ok, rk)
+    np.testing.assert_array_equal(ov, rv)
 
 
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
