@@ -26,6 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Sources the digit-pass kernel is compiled from: the HBM traffic measured with
+# hardware counters is reported only while they are unchanged.
+PASS_SOURCES = ("paper_1206_3511_amd/csrc/onesweep.hpp", "paper_1206_3511_amd/csrc/radix.hip",
+                "paper_1206_3511_amd/csrc/device_common.hpp", "paper_1206_3511_amd/csrc/internal.hpp")
+TRAFFIC_FILE = "profiles/onesweep_u32_100M_r8_hbm_traffic.md"
 DISTS = ("uniform", "small", "mid", "sorted", "reverse", "swaps", "gaussian")
 
 
@@ -79,6 +84,45 @@ def _kernel_avgs(ctx, fn, steps):
     return {k: sum(x) / len(x) for k, x in per.items()}
 
 
+def sources_digest(paths=PASS_SOURCES):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per digit-pass launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), or None when the
+    summary is missing or the kernel sources have changed since it was taken."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as f:
+            fields = dict(line.strip("- \n").split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
+        if fields.get("kernel_sources_sha256") != sources_digest():
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def calibrate_copy():
+    """One plain copy of known size for the counter calibration: sorting 2^28
+    equal keys skips every pass, so the only data movement is k_final_copy
+    reading and writing 1 GiB each."""
+    import torch
+
+    from paper_1206_3511_amd import intsort as I
+    z = torch.zeros(1 << 28, dtype=torch.uint32, device="cuda:0")
+    o = torch.empty_like(z)
+    for _ in range(2):
+        I.sort(z, out=o)
+    torch.cuda.synchronize()
+    del z, o
+    torch.cuda.empty_cache()
+
+
 def _roofline(kernel, bytes_per_launch, avg_ms, extra=None):
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     r = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -122,7 +166,8 @@ def run_plain(name, p, args):
         per_pass = 2 * n * w
         total = n * w + passes * per_pass
         roof = _roofline("k_onesweep (one digit pass)", per_pass, avg.get("pass", float("nan")),
-                         {"kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()},
+                         {"traffic": measured_traffic() if name == "uniform_u32_100M_radix_r8" else None,
+                          "kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()},
                           "sort_level_frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "algorithmic_bytes_per_sort": total})
     else:
@@ -346,12 +391,16 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving trace")
     ap.add_argument("--serve-buffers", type=int, default=96,
                     help="preallocated output buffers of 512 MB each for the serving trace")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB plain copy (for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     names = sorted(WORKLOADS) if args.workload == "all" else [args.workload]
+    if args.calibrate_copy:
+        calibrate_copy()
     for name in names:
         if name not in WORKLOADS:
             print(f"unknown workload {name}", file=sys.stderr)
