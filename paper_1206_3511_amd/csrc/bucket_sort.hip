@@ -169,7 +169,7 @@ static uint32_t scatter_bits(uint32_t) { return 8u; }
 constexpr uint32_t BUCKET_LDS_HIST_MAX = 16384;   // bucket_histogram_run's on-chip limit
 
 template <typename K>
-static uint64_t scatter_tile(uint32_t bits) { return bits == 11 ? PassCfg<K, 11>::TILE : PassCfg<K, 8>::TILE; }
+static uint64_t scatter_tile(uint32_t) { return PassCfg<K, 8>::TILE; }
 
 BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_options &o)
 {

@@ -84,6 +84,37 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     return res;
 }
 
+// Exclusive scan of one value per thread over NT threads with a single
+// barrier.  s_tmp needs NT/64 words and must not be written again before the
+// caller's next barrier.
+template <int NT>
+__device__ __forceinline__ uint32_t block_scan_1b(uint32_t v, uint32_t *s_tmp)
+{
+    constexpr int NW = NT / WAVE;
+    const uint32_t wave = threadIdx.x / WAVE;
+    const uint32_t incl = wave_inclusive_scan(v);
+    if (lane_id() == WAVE - 1) s_tmp[wave] = incl;
+    __syncthreads();
+    uint32_t below = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++)
+        if ((uint32_t)w < wave) below += s_tmp[w];
+    return below + incl - v;
+}
+
+// adds one to bin d of an LDS histogram; a wave whose active lanes all hold
+// the same bin adds once instead of colliding on one word
+__device__ __forceinline__ void lds_count(uint32_t *s_h, uint32_t d)
+{
+    const uint32_t d0 = first_lane_value(d);
+    const uint64_t act = ballot(true);
+    if (ballot(d != d0) == 0) {
+        if (mbcnt(act) == 0) atomicAdd(&s_h[d0], popc64(act));
+    } else {
+        atomicAdd(&s_h[d], 1u);
+    }
+}
+
 }  // namespace intsort
 
 namespace intsort {

@@ -72,6 +72,7 @@ struct RadixGeom {
     int passes;      // ceil(key_bits / r)
     int threads;     // workgroup size of the pass kernel
     int tile;        // keys per tile
+    bool chunked;    // reduce-then-scan passes over chunks of tiles
 };
 
 // where every region of a radix sort's workspace sits (byte offsets)
@@ -79,6 +80,7 @@ struct RadixLayout {
     RadixGeom g;
     uint64_t n;
     uint64_t num_tiles;
+    uint64_t status_words;   // words of each of the two status arrays
     size_t tmp_keys, tmp_vals, hist, excl, plan, counters, status0, status1, total;
 };
 

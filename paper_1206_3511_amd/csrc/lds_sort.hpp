@@ -118,7 +118,6 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
 
     uint32_t *wcnt = s_wcnt + wave * RADIX;
     uint64_t *bits = s_bits + wave * RADIX;
-    const uint64_t lanebit = 1ull << lane;
     for (int p = 0; p < PASSES; p++) {
         const uint32_t shift = 8u * (uint32_t)p;
         if (((diff >> shift) & 0xffu) == 0) continue;   // the same for every workgroup thread
@@ -131,7 +130,7 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
             const uint32_t d = lofs + j * WAVE < m ? digit_at<K>(k[j], shift, 0xffu) : 0xffu;
-            rk[j] = wave_rank<8>(d, wcnt, bits, lanebit, lane);
+            rk[j] = wave_rank<8>(d, wcnt, bits, lane);
         }
         __syncthreads();
         uint32_t tcnt[DPT];

@@ -20,6 +20,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "bucket_map.hpp"
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -57,10 +59,19 @@ __device__ __forceinline__ uint32_t digit_at(K k, uint32_t shift, uint32_t mask)
 
 // digit p of radix sort: (k >> p*r) & (2^r - 1)
 struct RadixDigit {
+    // an all-ones key has the largest digit: padding past a tile's end needs
+    // no separate check
+    static constexpr bool ONES_IS_MAX = true;
     uint32_t shift, mask;
     __device__ RadixDigit prepare() const { return *this; }
     template <typename K>
     __device__ __forceinline__ uint32_t operator()(K k) const { return digit_at<K>(k, shift, mask); }
+    // bits lo .. lo+w-1 of the digit
+    template <typename K>
+    __device__ __forceinline__ uint32_t sub(K k, uint32_t lo, uint32_t w) const
+    {
+        return (uint32_t)(k >> (shift + lo)) & ((1u << w) - 1u);
+    }
 };
 
 // an 8-bit field of the bucket index b(k) of bucket sort; min and max are
@@ -69,6 +80,7 @@ struct BucketDigitArgs {
     const uint64_t *minmax;
     uint32_t buckets, shift, mask;
     struct Fn {
+        static constexpr bool ONES_IS_MAX = false;
         BucketMap m;
         uint32_t shift, mask;
         template <typename K>
@@ -189,8 +201,7 @@ struct DescTiles {
 // digits wider than 8 bits the bitmap is indexed by the low 8 bits and the
 // remaining bits are matched with ballots.
 template <int BITS>
-__device__ __forceinline__ uint32_t wave_rank(uint32_t d, uint32_t *wcnt, uint64_t *bits, uint64_t lanebit,
-                                              uint32_t lane)
+__device__ __forceinline__ uint32_t wave_rank(uint32_t d, uint32_t *wcnt, uint64_t *bits, uint32_t lane)
 {
     const uint32_t d0 = first_lane_value(d);
     // the active lanes, taken before any branch: a ballot inside a branch
@@ -206,7 +217,9 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, uint32_t *wcnt, uint64
         wave_sync();
     } else {
         const uint32_t h = BITS > 8 ? (d & 255u) : d;
-        atomicOr(reinterpret_cast<unsigned long long *>(&bits[h]), (unsigned long long)lanebit);
+        // each half of the wave sets its bit in its own 32-bit half of the
+        // 64-bit peer mask (half the LDS bytes of a 64-bit OR)
+        atomicOr(reinterpret_cast<uint32_t *>(&bits[h]) + (lane >> 5), 1u << (lane & 31));
         wave_sync();
         uint64_t peers = __hip_atomic_load(&bits[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         if (BITS > 8) {
@@ -356,7 +369,6 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
 
     __shared__ alignas(16) unsigned char s_raw[TILE * sizeof(K)];
     __shared__ uint32_t s_wcnt[WAVES * RADIX];
-    __shared__ uint32_t s_tile_excl[RADIX];
     __shared__ uint32_t s_gbase[RADIX];
     __shared__ uint32_t s_scan[NT / WAVE + 1];
     __shared__ uint32_t s_tile;
@@ -416,10 +428,13 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     const uint32_t lofs = wave * (IPT * WAVE) + lane;   // tile-local index of item 0
     const uint32_t wofs = ti.start + lofs;
     if (valid == (uint32_t)TILE) {
+        // one base address per thread, item offsets as immediates
+        const K *sp = src + wofs;
+        const uint32_t *vp = PAIRS ? vsrc + wofs : nullptr;
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
-            k[j] = src[wofs + j * WAVE];
-            if (PAIRS) v[j] = vsrc[wofs + j * WAVE];
+            k[j] = sp[j * WAVE];
+            if (PAIRS) v[j] = vp[j * WAVE];
         }
     } else {
 #pragma unroll
@@ -430,7 +445,9 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         }
     }
     // keys past the end of the tile take the largest digit and so rank last
+    using DG = std::remove_cv_t<decltype(dg)>;
     auto digit_of = [&](int j) -> uint32_t {
+        if (DG::ONES_IS_MAX) return dg(k[j]);
         return (valid == (uint32_t)TILE || lofs + j * WAVE < valid) ? dg(k[j]) : MASK;
     };
 
@@ -438,9 +455,8 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     uint32_t rk[IPT];
     uint32_t *wcnt = s_wcnt + wave * RADIX;
     uint64_t *bits = s_bits + wave * BM;
-    const uint64_t lanebit = 1ull << lane;
 #pragma unroll
-    for (int j = 0; j < IPT; j++) rk[j] = wave_rank<BITS>(digit_of(j), wcnt, bits, lanebit, lane);
+    for (int j = 0; j < IPT; j++) rk[j] = wave_rank<BITS>(digit_of(j), wcnt, bits, lane);
     __syncthreads();
 
     // ---- per digit: offsets of every wave inside the tile and the tile's
@@ -471,7 +487,12 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     for (int i = 0; i < DPT; i++) {
         const uint32_t d = tid * DPT + i;
         if (i > 0) texcl[i] = texcl[i - 1] + tcnt[i - 1];
-        if (d < (uint32_t)RADIX) s_tile_excl[d] = texcl[i];
+        if (d < (uint32_t)RADIX) {
+            // every wave's offset of the digit inside the tile, so that the
+            // reorder reads one word per key
+#pragma unroll
+            for (int w = 0; w < WAVES; w++) s_wcnt[w * RADIX + d] += texcl[i];
+        }
     }
     __syncthreads();
 
@@ -480,7 +501,7 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
         const uint32_t d = digit_of(j);
-        rk[j] += s_tile_excl[d] + s_wcnt[wave * RADIX + d];
+        rk[j] += s_wcnt[wave * RADIX + d];
         s_stage[rk[j]] = k[j];
     }
 

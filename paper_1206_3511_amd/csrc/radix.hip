@@ -29,9 +29,12 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "intsort.h"
 #include "internal.hpp"
+#include "chunk_sort.hpp"
 #include "onesweep.hpp"
 
 namespace intsort {
@@ -74,20 +77,6 @@ struct HistArgs {
     uint32_t copies;       // histogram copies the workgroups spread their adds over
 };
 
-// add one key's digit for pass p to the LDS histogram; a wave whose lanes all
-// hold the same digit adds once instead of colliding 64 times on one word
-template <int RADIX>
-__device__ __forceinline__ void hist_add(uint32_t *s_h, uint32_t d)
-{
-    const uint32_t d0 = first_lane_value(d);
-    const uint64_t act = ballot(true);
-    if (ballot(d != d0) == 0) {
-        if (mbcnt(act) == 0) atomicAdd(&s_h[d0], popc64(act));
-    } else {
-        atomicAdd(&s_h[d], 1u);
-    }
-}
-
 template <typename K, int BITS>
 __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__restrict__ keys, HistArgs a)
 {
@@ -127,7 +116,7 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
                 for (int e = 0; e < KPV; e++) {
 #pragma unroll
                     for (int p = 0; p < PASSES; p++)
-                        hist_add<RADIX>(s_h + p * RADIX, digit_at<K>(x[u].v[e], (uint32_t)(p * BITS), MASK));
+                        lds_count(s_h + p * RADIX, digit_at<K>(x[u].v[e], (uint32_t)(p * BITS), MASK));
                 }
             }
         }
@@ -137,7 +126,7 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
             K k = keys[i];
 #pragma unroll
             for (int p = 0; p < PASSES; p++)
-                hist_add<RADIX>(s_h + p * RADIX, digit_at<K>(k, (uint32_t)(p * BITS), MASK));
+                lds_count(s_h + p * RADIX, digit_at<K>(k, (uint32_t)(p * BITS), MASK));
         }
     }
     __syncthreads();
@@ -237,11 +226,20 @@ __global__ __launch_bounds__(256) void k_final_copy(const K *in, K *out, K *tmp,
 
 // ------------------------------------------------------------------ host
 
+// 11-bit digits take the chunked reduce-then-scan pass, narrower ones the
+// onesweep pass
+template <int BITS>
+constexpr bool chunked_pass() { return BITS == 11; }
+
 template <typename K, int BITS>
 static RadixGeom geom_of()
 {
     using C = PassCfg<K, BITS>;
-    return RadixGeom{BITS, C::RADIX, C::PASSES, C::NT, C::TILE};
+    if (chunked_pass<BITS>()) {
+        using H = ChunkCfg<K, BITS>;
+        return RadixGeom{BITS, H::RADIX, C::PASSES, H::NT, H::TILE, true};
+    }
+    return RadixGeom{BITS, C::RADIX, C::PASSES, C::NT, C::TILE, false};
 }
 
 RadixGeom radix_geometry(int key_bytes, int bits)
@@ -270,8 +268,16 @@ RadixLayout radix_layout(int key_bytes, bool pairs, uint64_t n, int bits)
     L.hist = take((size_t)HIST_COPIES * L.g.passes * L.g.radix * 4);
     L.excl = take((size_t)L.g.passes * L.g.radix * 4);
     L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
-    L.status0 = take((size_t)L.num_tiles * (L.g.radix + 1) * 4);
-    L.status1 = take((size_t)L.num_tiles * (L.g.radix + 1) * 4);
+    if (L.g.chunked) {
+        // per chunk and digit: counts, and where the chunk's runs start
+        const uint64_t chunks = std::min<uint64_t>(L.num_tiles, ChunkCfg<uint32_t, 11>::MAX_CHUNKS);
+        L.status_words = chunks * (uint64_t)L.g.radix;
+    } else {
+        // per tile and digit: look-back words, then one flag per tile
+        L.status_words = L.num_tiles * (uint64_t)(L.g.radix + 1);
+    }
+    L.status0 = take((size_t)L.status_words * 4);
+    L.status1 = take((size_t)L.status_words * 4);
     L.total = off;
     return L;
 }
@@ -316,7 +322,7 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
     h.plan = reinterpret_cast<uint32_t *>(ws + L.plan);
     h.counters = counters;
     h.status0 = finalize ? reinterpret_cast<uint32_t *>(ws + L.status0) : nullptr;
-    h.status0_words = finalize ? L.num_tiles * (uint64_t)(C::RADIX + 1) : 0;
+    h.status0_words = finalize ? L.status_words : 0;
     h.n = (uint32_t)c.n;
     h.max_passes = (uint32_t)c.max_passes;
     h.skip = c.skip_constant_digits ? 1u : 0u;
@@ -366,9 +372,28 @@ static hipError_t run_typed(const RadixCall &c, hipStream_t s)
         a.plan = plan + p * PLAN_WORDS;
         a.pass = (uint32_t)p;
         const RadixDigit dg{(uint32_t)(p * BITS), (uint32_t)(C::RADIX - 1)};
-        const PlainTiles tl{(uint32_t)c.n, (uint32_t)L.num_tiles, excl + p * C::RADIX};
-        hipLaunchKernelGGL((k_onesweep<K, BITS, PAIRS, RadixDigit, PlainTiles>), dim3((uint32_t)L.num_tiles),
-                           dim3(C::NT), 0, s, a, dg, tl);
+        if constexpr (chunked_pass<BITS>()) {
+            using H = ChunkCfg<K, BITS>;
+            ChunkArgs ca{};
+            ca.plan = a.plan;
+            ca.n = (uint32_t)c.n;
+            ca.tiles = (uint32_t)L.num_tiles;
+            const uint64_t want =
+                std::min<uint64_t>({L.num_tiles, (uint64_t)current_cus() * H::WG_PER_CU, (uint64_t)H::MAX_CHUNKS});
+            ca.tpc = (uint32_t)((L.num_tiles + want - 1) / want);
+            ca.chunks = (uint32_t)((L.num_tiles + ca.tpc - 1) / ca.tpc);
+            ca.cnt = a.status0;
+            ca.off = a.status1;
+            ca.excl = excl + p * C::RADIX;
+            ca.counters = a.counters;
+            hipLaunchKernelGGL((k_chunk_count<K, BITS>), dim3(ca.chunks), dim3(512), 0, s, a, ca, dg);
+            hipLaunchKernelGGL(k_chunk_scan, dim3(C::RADIX), dim3(256), 0, s, ca, (uint32_t)C::RADIX);
+            hipLaunchKernelGGL((k_chunk_sort<K, BITS, PAIRS>), dim3(ca.chunks), dim3(H::NT), 0, s, a, ca, dg);
+        } else {
+            const PlainTiles tl{(uint32_t)c.n, (uint32_t)L.num_tiles, excl + p * C::RADIX};
+            hipLaunchKernelGGL((k_onesweep<K, BITS, PAIRS, RadixDigit, PlainTiles>), dim3((uint32_t)L.num_tiles),
+                               dim3(C::NT), 0, s, a, dg, tl);
+        }
         if (c.timer) c.timer->mark(INTSORT_KERNEL_PASS, (uint32_t)p, s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

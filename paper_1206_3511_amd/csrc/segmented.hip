@@ -145,18 +145,6 @@ __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segm
 
 // per listed tile: the digit counts of every pass (one read of its keys);
 // also clears the tile's look-back words for the first pass
-template <int RADIX>
-__device__ __forceinline__ void seg_hist_add(uint32_t *s_h, uint32_t d)
-{
-    const uint32_t d0 = first_lane_value(d);
-    const uint64_t act = ballot(true);
-    if (ballot(d != d0) == 0) {
-        if (mbcnt(act) == 0) atomicAdd(&s_h[d0], popc64(act));
-    } else {
-        atomicAdd(&s_h[d], 1u);
-    }
-}
-
 template <typename K>
 __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__restrict__ keys, SegWs w)
 {
@@ -173,7 +161,7 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
     for (uint32_t i = threadIdx.x; i < d.count; i += SEG_HIST_THREADS) {
         const K k = kp[d.start + i];
 #pragma unroll
-        for (int p = 0; p < PASSES; p++) seg_hist_add<256>(s_h + p * 256, digit_at<K>(k, 8u * p, 0xffu));
+        for (int p = 0; p < PASSES; p++) lds_count(s_h + p * 256, digit_at<K>(k, 8u * p, 0xffu));
     }
     __syncthreads();
     uint32_t *out = w.tile_hist + (uint64_t)t * PASSES * 256;
