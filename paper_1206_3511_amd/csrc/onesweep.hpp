@@ -101,6 +101,7 @@ struct TileInfo {
     void *out;
     void *tmp;
     uint32_t limit;       // every store index stays below this
+    uint32_t slot;        // segment row (segmented tiles only)
 };
 
 // one array of n keys in tiles of TILE keys
@@ -118,6 +119,8 @@ struct PlainTiles {
         ti.excl = excl;
         return true;
     }
+    // every tile runs the pass with the buffers of the pass's plan
+    __device__ bool route(const TileInfo &, uint32_t, uint32_t &, uint32_t &) const { return true; }
     __device__ bool missing_is_error() const { return true; }
     __device__ uint32_t listed() const { return num_tiles; }
 };
@@ -133,11 +136,39 @@ struct TileDesc {
     uint32_t pad[3];
 };
 
+// Which buffers an active pass of one segment reads and writes, when the
+// segment runs only the passes in `mask` (the others have a constant digit
+// inside it): the last active pass lands in the output, or, in place, the
+// passes alternate scratch / output starting with the scratch.
+__device__ __forceinline__ void segment_route(uint32_t mask, uint32_t pass, bool in_place, uint32_t &srcc,
+                                              uint32_t &dstc)
+{
+    const uint32_t A = (uint32_t)__popc(mask);
+    auto dst_of = [&](uint32_t q) -> uint32_t {
+        if (in_place) return (q % 2 == 0) ? BUF_TMP : BUF_OUT;
+        return ((A - 1 - q) % 2 == 0) ? BUF_OUT : BUF_TMP;
+    };
+    const uint32_t q = (uint32_t)__popc(mask & ((1u << pass) - 1u));
+    srcc = q == 0 ? BUF_IN : dst_of(q - 1);
+    dstc = dst_of(q);
+}
+
+// where a segment's keys are after its active passes
+__device__ __forceinline__ uint32_t segment_result(uint32_t mask, bool in_place)
+{
+    const uint32_t A = (uint32_t)__popc(mask);
+    if (A == 0) return BUF_IN;
+    if (in_place) return ((A - 1) % 2 == 0) ? BUF_TMP : BUF_OUT;
+    return BUF_OUT;
+}
+
 struct SegTiles {
     const TileDesc *desc;
     const uint32_t *num_tiles;   // device count of listed tiles
     const uint32_t *seg_excl;    // [slot][radix] for this pass
     uint32_t radix;
+    const uint32_t *slot_mask;   // [slot] passes the segment runs
+    uint32_t in_place;
     template <int TILE>
     __device__ __forceinline__ bool get(uint32_t t, TileInfo &ti) const
     {
@@ -148,6 +179,14 @@ struct SegTiles {
         ti.first_tile = d.first_tile;
         ti.base = d.base;
         ti.excl = seg_excl + (uint64_t)d.slot * radix;
+        ti.slot = d.slot;
+        return true;
+    }
+    __device__ bool route(const TileInfo &ti, uint32_t pass, uint32_t &srcc, uint32_t &dstc) const
+    {
+        const uint32_t mask = slot_mask[ti.slot];
+        if (!((mask >> pass) & 1u)) return false;
+        segment_route(mask, pass, in_place != 0, srcc, dstc);
         return true;
     }
     __device__ bool missing_is_error() const { return false; }
@@ -169,6 +208,8 @@ struct DescTiles {
     const uint32_t *num_tiles;
     const uint32_t *seg_excl;
     uint32_t radix;
+    const uint32_t *slot_mask;
+    uint32_t in_place;        // unused: each array says for itself
     const SegBuf *bufs;       // [slot]
     template <int TILE>
     __device__ __forceinline__ bool get(uint32_t t, TileInfo &ti) const
@@ -185,6 +226,14 @@ struct DescTiles {
         ti.out = b.out;
         ti.tmp = b.tmp;
         ti.limit = (uint32_t)b.n;
+        ti.slot = d.slot;
+        return true;
+    }
+    __device__ bool route(const TileInfo &ti, uint32_t pass, uint32_t &srcc, uint32_t &dstc) const
+    {
+        const uint32_t mask = slot_mask[ti.slot];
+        if (!((mask >> pass) & 1u)) return false;
+        segment_route(mask, pass, ti.in == ti.out, srcc, dstc);
         return true;
     }
     __device__ bool missing_is_error() const { return false; }
@@ -376,13 +425,8 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     uint64_t *s_bits = reinterpret_cast<uint64_t *>(s_raw);
 
     if (a.plan[0] == 0) return;   // pass skipped: the same for every workgroup
-    const uint32_t srcc = a.plan[1], dstc = a.plan[2], ord = a.plan[3];
-    const uint32_t *vsrc = nullptr;
-    uint32_t *vdst = nullptr;
-    if (PAIRS) {
-        vsrc = srcc == BUF_IN ? a.vin : (srcc == BUF_OUT ? a.vout : a.vtmp);
-        vdst = dstc == BUF_OUT ? a.vout : a.vtmp;
-    }
+    uint32_t srcc = a.plan[1], dstc = a.plan[2];
+    const uint32_t ord = a.plan[3];
     uint32_t *status = (ord & 1) ? a.status1 : a.status0;
     uint32_t *status_next = (ord & 1) ? a.status0 : a.status1;
     // per-tile "inclusive words published" flags follow each status array
@@ -412,6 +456,19 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         if (tid == 0 && (tile >= a.tile_capacity || tl.missing_is_error()))
             atomicOr(&a.counters[CTR_ERROR], DEVERR_BAD_TILE);
         return;
+    }
+    if (!tl.route(ti, a.pass, srcc, dstc)) {
+        // the tile's segment has a constant digit here: nothing moves, but
+        // the tile's look-back words for the next pass start clear
+        for (uint32_t d = tid; d < (uint32_t)RADIX; d += NT) store_agent(&status_next[(uint64_t)tile * RADIX + d], 0u);
+        if (tid == 0) store_agent(&tflag_next[tile], 0u);
+        return;
+    }
+    const uint32_t *vsrc = nullptr;
+    uint32_t *vdst = nullptr;
+    if (PAIRS) {
+        vsrc = srcc == BUF_IN ? a.vin : (srcc == BUF_OUT ? a.vout : a.vtmp);
+        vdst = dstc == BUF_OUT ? a.vout : a.vtmp;
     }
     for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
     for (uint32_t i = tid; i < (uint32_t)(WAVES * BM); i += NT) s_bits[i] = 0;

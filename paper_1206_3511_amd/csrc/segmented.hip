@@ -11,7 +11,9 @@
 //                                 segment into digit offsets, then every
 //                                 digit pass runs k_onesweep over the tile
 //                                 list with its look-back bounded by the
-//                                 segment's first tile.
+//                                 segment's first tile.  A segment skips
+//                                 the passes whose digit is constant inside
+//                                 it, with its own scratch/output ping-pong.
 // Every launch has a grid sized for the most work the class can hold; work
 // groups past the class's device-side count return at once.  Each segment is
 // sorted with the stable LSD radix sort of section 2.5 (Algorithm 4), so the
@@ -60,14 +62,16 @@ struct SegWs {
     SegBuf *bufs;             // [slot_cap] separate arrays only, else null
     void *tmp;                // scratch keys of the large segments
     uint32_t lds_cutoff;      // longer segments take the multi-workgroup path
+    uint32_t *slot_mask;      // [slot_cap] digit passes each large segment runs
+    uint32_t skip;            // leave out passes whose digit is constant in the segment
 };
 
 // One thread per segment: classify by size; a large segment reserves a run
 // of consecutive tile ids and writes their descriptors (and, for separate
 // arrays, its buffers and a slice of the scratch buffer).  Thread 0 also
-// writes the plan of the digit passes: all of them run, alternating between
-// the scratch and the output buffer so that the last (an odd pass: there are
-// 4 or 8) lands in the output.
+// writes the plan words of the digit passes: every pass is launched (its
+// ordinal picks the look-back words); which buffers a tile reads and writes
+// follow from the passes its own segment runs.
 template <typename K, class Src>
 __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segments, SegWs w, uint32_t passes)
 {
@@ -174,16 +178,55 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegWs w)
 {
     constexpr int PASSES = (int)sizeof(K);
     __shared__ uint32_t s_scan[256 / WAVE + 1];
+    __shared__ uint32_t s_const;
     const uint32_t slot = blockIdx.x;
     if (slot >= w.counters[CTR_SEG_SLOTS] || slot >= w.slot_cap) return;
     const uint32_t first = w.slot_first[slot], nt = w.slot_ntiles[slot];
     const uint32_t d = threadIdx.x;
+    uint32_t mask = 0;
     for (int p = 0; p < PASSES; p++) {
         uint32_t c = 0;
         for (uint32_t t = 0; t < nt; t++) c += w.tile_hist[((uint64_t)(first + t) * PASSES + p) * 256 + d];
+        if (d == 0) s_const = 0;
         uint32_t total;
         const uint32_t ex = block_exclusive_scan<256>(c, s_scan, &total);
         w.seg_excl[((uint64_t)p * w.slot_cap + slot) * 256 + d] = ex;
+        // a digit that takes one value in the whole segment leaves the
+        // segment's order as it is: the pass has nothing to do for it
+        if (c == total) s_const = 1;
+        __syncthreads();
+        if (!(w.skip && s_const)) mask |= 1u << p;
+        __syncthreads();
+    }
+    if (d == 0) w.slot_mask[slot] = mask;
+}
+
+// Moves every large segment whose keys did not end in the output there: all
+// its digits were constant (and the sort is out of place), or in place with
+// an odd number of passes run, which left them in the scratch buffer.
+template <typename K, bool PAIRS, class TilesT>
+__global__ __launch_bounds__(256) void k_seg_final_copy(PassArgs<K> a, TilesT tl)
+{
+    constexpr int TILE = PassCfg<K, 8>::TILE;
+    if (blockIdx.x >= tl.listed()) return;
+    TileInfo ti;
+    ti.in = a.in;
+    ti.out = a.out;
+    ti.tmp = a.tmp;
+    ti.limit = a.n;
+    if (!tl.template get<TILE>(blockIdx.x, ti)) return;
+    const bool in_place = ti.in == ti.out;
+    const uint32_t where = segment_result(tl.slot_mask[ti.slot], in_place);
+    if (where == BUF_OUT || (where == BUF_IN && in_place)) return;
+    const K *src = static_cast<const K *>(where == BUF_IN ? ti.in : ti.tmp);
+    K *dst = static_cast<K *>(ti.out);
+    const uint32_t *vsrc = where == BUF_IN ? a.vin : a.vtmp;
+    for (uint32_t i = threadIdx.x; i < ti.count; i += 256) {
+        const uint32_t g = ti.start + i;
+        if (g < ti.limit) {
+            dst[g] = src[g];
+            if (PAIRS) a.vout[g] = vsrc[g];
+        }
     }
 }
 
@@ -218,6 +261,7 @@ static SegLayout seg_layout_typed(uint64_t n, uint64_t S, uint32_t cutoff_req)
     L.bufs = take((size_t)L.slot_cap * sizeof(SegBuf));
     L.tile_hist = take((size_t)L.tile_cap * PASSES * 256 * 4);
     L.seg_excl = take((size_t)PASSES * L.slot_cap * 256 * 4);
+    L.slot_mask = take((size_t)L.slot_cap * 4);
     L.status0 = take((size_t)L.tile_cap * 257 * 4);
     L.status1 = take((size_t)L.tile_cap * 257 * 4);
     L.tmp_keys = take(n * sizeof(K));
@@ -273,6 +317,8 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     w.bufs = separate ? reinterpret_cast<SegBuf *>(ws + L.bufs) : nullptr;
     w.tmp = ws + L.tmp_keys;
     w.lds_cutoff = L.lds_cutoff;
+    w.slot_mask = reinterpret_cast<uint32_t *>(ws + L.slot_mask);
+    w.skip = (c.opts.flags & INTSORT_FLAG_NO_PASS_SKIP) ? 0u : 1u;
 
     if (tm) tm->start(s);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, w.counters, (uint64_t)CTR_WORDS, 0u);
@@ -330,20 +376,24 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     a.counters = w.counters;
     a.n = (uint32_t)c.n;
     a.tile_capacity = L.tile_cap;
+    TilesT tl{};
+    tl.desc = w.tiles;
+    tl.num_tiles = w.counters + CTR_SEG_TILES;
+    tl.radix = 256u;
+    tl.slot_mask = w.slot_mask;
+    tl.in_place = c.keys_in == c.keys_out ? 1u : 0u;
+    set_bufs(tl, w.bufs);
     for (int p = 0; p < PASSES; p++) {
         a.plan = w.plan + p * PLAN_WORDS;
         a.pass = (uint32_t)p;
         const RadixDigit dg{(uint32_t)(8 * p), 0xffu};
-        TilesT tl{};
-        tl.desc = w.tiles;
-        tl.num_tiles = w.counters + CTR_SEG_TILES;
         tl.seg_excl = w.seg_excl + (uint64_t)p * L.slot_cap * 256;
-        tl.radix = 256u;
-        set_bufs(tl, w.bufs);
         hipLaunchKernelGGL((k_onesweep<K, 8, PAIRS, RadixDigit, TilesT>), dim3(L.tile_cap), dim3(PC::NT), 0, s,
                            a, dg, tl);
         if (tm) tm->mark(INTSORT_KERNEL_PASS, (uint32_t)p, s);
     }
+    hipLaunchKernelGGL((k_seg_final_copy<K, PAIRS, TilesT>), dim3(L.tile_cap), dim3(256), 0, s, a, tl);
+    if (tm) tm->mark(INTSORT_KERNEL_COPY, 1, s);
     return hipGetLastError();
 }
 
