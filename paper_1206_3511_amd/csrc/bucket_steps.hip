@@ -11,7 +11,10 @@
 
 namespace intsort {
 
-constexpr int MM_THREADS = 256;
+// one workgroup per CU: every workgroup ends with one atomic min and max on
+// the same two words, so fewer, larger workgroups queue less there
+constexpr int MM_THREADS = 1024;
+constexpr int MM_UNROLL = 4;
 
 __global__ void k_minmax_init(uint64_t *minmax)
 {
@@ -30,16 +33,26 @@ __global__ __launch_bounds__(MM_THREADS) void k_minmax(const K *__restrict__ key
     __shared__ uint64_t s_min[MM_THREADS / WAVE], s_max[MM_THREADS / WAVE];
     K lo = ~K(0), hi = 0;
     const uint64_t nvec = n / KPV;
-    const uint64_t stride = (uint64_t)gridDim.x * MM_THREADS;
     const Vec *vk = reinterpret_cast<const Vec *>(keys);
-    for (uint64_t v = (uint64_t)blockIdx.x * MM_THREADS + threadIdx.x; v < nvec; v += stride) {
-        Vec x = vk[v];
+    // MM_UNROLL 16-byte loads in flight per thread
+    const uint64_t step = (uint64_t)gridDim.x * MM_THREADS * MM_UNROLL;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * MM_THREADS * MM_UNROLL + threadIdx.x; v0 < nvec; v0 += step) {
+        Vec x[MM_UNROLL];
 #pragma unroll
-        for (int e = 0; e < KPV; e++) {
-            lo = x.v[e] < lo ? x.v[e] : lo;
-            hi = x.v[e] > hi ? x.v[e] : hi;
+        for (int u = 0; u < MM_UNROLL; u++)
+            if (v0 + (uint64_t)u * MM_THREADS < nvec) x[u] = vk[v0 + (uint64_t)u * MM_THREADS];
+#pragma unroll
+        for (int u = 0; u < MM_UNROLL; u++) {
+            if (v0 + (uint64_t)u * MM_THREADS < nvec) {
+#pragma unroll
+                for (int e = 0; e < KPV; e++) {
+                    lo = x[u].v[e] < lo ? x[u].v[e] : lo;
+                    hi = x[u].v[e] > hi ? x[u].v[e] : hi;
+                }
+            }
         }
     }
+    const uint64_t stride = (uint64_t)gridDim.x * MM_THREADS;
     for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * MM_THREADS + threadIdx.x; i < n; i += stride) {
         lo = keys[i] < lo ? keys[i] : lo;
         hi = keys[i] > hi ? keys[i] : hi;
@@ -69,8 +82,8 @@ hipError_t minmax_run(int key_bytes, const void *keys, uint64_t n, uint64_t *min
 {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    uint64_t blocks = (n / (16 / key_bytes) + MM_THREADS - 1) / MM_THREADS;
-    const uint64_t cap = (uint64_t)device_cu_count(dev) * 4;
+    uint64_t blocks = (n / (16 / key_bytes) + MM_THREADS * MM_UNROLL - 1) / (MM_THREADS * MM_UNROLL);
+    const uint64_t cap = (uint64_t)device_cu_count(dev);
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(1), 0, s, minmax);
@@ -86,6 +99,7 @@ hipError_t minmax_run(int key_bytes, const void *keys, uint64_t n, uint64_t *min
 // ------------------------------------------------------- bucket histogram
 
 constexpr int BH_THREADS = 512;
+constexpr int BH_UNROLL = 2;
 constexpr uint32_t BH_LDS_BUCKETS = 16384;   // 64 KB of LDS counters
 
 __global__ void k_zero_u32(uint32_t *p, uint32_t n)
@@ -104,21 +118,32 @@ __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__rest
         for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) s_c[i] = 0;
         __syncthreads();
     }
-    const uint64_t stride = (uint64_t)gridDim.x * BH_THREADS;
-    for (uint64_t i = (uint64_t)blockIdx.x * BH_THREADS + threadIdx.x; i < n; i += stride) {
-        const uint32_t b = bucket_of(m, keys[i]);
-        if (LDS) {
-            const uint32_t b0 = first_lane_value(b);
-            const uint64_t act = ballot(true);
-            if (ballot(b != b0) == 0) {
-                if (mbcnt(act) == 0) atomicAdd(&s_c[b0], popc64(act));
-            } else {
-                atomicAdd(&s_c[b], 1u);
+    auto count = [&](K k) {
+        const uint32_t b = bucket_of(m, k);
+        if (LDS) lds_count(s_c, b);
+        else atomicAdd(&counts[b], 1u);
+    };
+    constexpr int KPV = 16 / (int)sizeof(K);
+    struct alignas(16) Vec { K v[KPV]; };
+    const uint64_t nvec = n / KPV;
+    const Vec *vk = reinterpret_cast<const Vec *>(keys);
+    // BH_UNROLL 16-byte loads in flight per thread
+    const uint64_t step = (uint64_t)gridDim.x * BH_THREADS * BH_UNROLL;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * BH_THREADS * BH_UNROLL + threadIdx.x; v0 < nvec; v0 += step) {
+        Vec x[BH_UNROLL];
+#pragma unroll
+        for (int u = 0; u < BH_UNROLL; u++)
+            if (v0 + (uint64_t)u * BH_THREADS < nvec) x[u] = vk[v0 + (uint64_t)u * BH_THREADS];
+#pragma unroll
+        for (int u = 0; u < BH_UNROLL; u++) {
+            if (v0 + (uint64_t)u * BH_THREADS < nvec) {
+#pragma unroll
+                for (int e = 0; e < KPV; e++) count(x[u].v[e]);
             }
-        } else {
-            atomicAdd(&counts[b], 1u);
         }
     }
+    const uint64_t stride = (uint64_t)gridDim.x * BH_THREADS;
+    for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * BH_THREADS + threadIdx.x; i < n; i += stride) count(keys[i]);
     if (LDS) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) {
@@ -134,7 +159,7 @@ hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, con
     int dev = 0;
     (void)hipGetDevice(&dev);
     hipLaunchKernelGGL(k_zero_u32, dim3((B + 255) / 256), dim3(256), 0, s, counts, B);
-    uint64_t blocks = (n + BH_THREADS - 1) / BH_THREADS;
+    uint64_t blocks = (n / (16 / key_bytes) + BH_THREADS * BH_UNROLL - 1) / (BH_THREADS * BH_UNROLL);
     const uint64_t cap = (uint64_t)device_cu_count(dev) * 2;
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;

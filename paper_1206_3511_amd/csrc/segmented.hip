@@ -162,10 +162,23 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
     for (uint32_t i = threadIdx.x; i < 256u; i += SEG_HIST_THREADS) w.status0[(uint64_t)t * 256 + i] = 0;
     if (threadIdx.x == 0) w.status0[(uint64_t)w.tile_cap * 256 + t] = 0;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < d.count; i += SEG_HIST_THREADS) {
-        const K k = kp[d.start + i];
+    // U loads in flight per thread (segments start anywhere, so 4- or
+    // 8-byte loads)
+    constexpr int U = 8;
+    for (uint32_t i0 = threadIdx.x; i0 < d.count; i0 += SEG_HIST_THREADS * U) {
+        K x[U];
 #pragma unroll
-        for (int p = 0; p < PASSES; p++) lds_count(s_h + p * 256, digit_at<K>(k, 8u * p, 0xffu));
+        for (int u = 0; u < U; u++) {
+            const uint32_t i = i0 + u * SEG_HIST_THREADS;
+            x[u] = i < d.count ? kp[d.start + i] : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (i0 + u * SEG_HIST_THREADS < d.count) {
+#pragma unroll
+                for (int p = 0; p < PASSES; p++) lds_count(s_h + p * 256, digit_at<K>(x[u], 8u * p, 0xffu));
+            }
+        }
     }
     __syncthreads();
     uint32_t *out = w.tile_hist + (uint64_t)t * PASSES * 256;
