@@ -123,6 +123,19 @@ def calibrate_copy():
     torch.cuda.empty_cache()
 
 
+def _memory(width, has_values, n, segments=0, **opt):
+    """Device bytes one call of the workload holds: its input and output
+    buffers and the workspace the library asks for (the analogue of the
+    paper's memory table)."""
+    from paper_1206_3511_amd import intsort as I
+    ctx = I.context(-1)   # planning context: sizes only
+    kt = I.U32 if width == 4 else I.U64
+    ws = ctx.workspace_size(kt, has_values, n, segments, I.make_options(**opt))
+    io = n * (width + (4 if has_values else 0))
+    return {"workspace_bytes": int(ws), "input_bytes": int(io), "output_bytes": int(io),
+            "peak_device_bytes": int(ws + 2 * io), "workspace_bytes_per_key": round(ws / max(n, 1), 3)}
+
+
 def _roofline(kernel, bytes_per_launch, avg_ms, extra=None):
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     r = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -181,9 +194,10 @@ def run_plain(name, p, args):
         cpu = cpu_baseline(keys_h, algo, bits, B, args)
     metric = "Gkeys/s at 100M uint32 (LSD radix, 8-bit digits)" if name == "uniform_u32_100M_radix_r8" else \
         f"Gkeys/s ({algo}, {n} uint32 keys)"
+    mem = _memory(4, False, n, algo=algo, digit_bits=bits, num_buckets=B)
     return _line(metric, value, "Gkeys/s", ms, args.steps, args.warmup, "u32",
                  {"workload": name, "n": n, "distribution": DISTS[p["dist"]], "algo": algo, "digit_bits": bits,
-                  "num_buckets": B or None}, roof, cpu, output_matches_library_sort=ok)
+                  "num_buckets": B or None}, roof, cpu, output_matches_library_sort=ok, memory=mem)
 
 
 def cpu_baseline(keys_h, algo, bits, B, args):
@@ -230,13 +244,16 @@ def run_pairs(name, p, args):
     value = n / (ms * 1e-3) / 1e9
     avg = _kernel_avgs(ctx, fn, steps)
     kind = "pass" if algo == "radix" else "bucket_scatter"
-    roof = _roofline(f"k_onesweep (pairs, {algo})", 2 * n * 12, avg.get(kind, float("nan")),
+    kname = ("k_chunk_count + k_chunk_scan + k_chunk_sort (one 11-bit pass, pairs)" if algo == "radix" and bits == 11
+             else f"k_onesweep (one pass, pairs, {algo})")
+    roof = _roofline(kname, 2 * n * 12, avg.get(kind, float("nan")),
                      {"kernel_avg_ms": {kk: round(x, 5) for kk, x in avg.items()}})
     order = np.argsort(kh, kind="stable")
     good = bool(np.array_equal(ok_.cpu().numpy(), kh[order]) and np.array_equal(ov_.cpu().numpy(), vh[order]))
     return _line(f"Gkeys/s ({algo} pairs, 100M uint64 keys + uint32 payload)", value, "Gkeys/s", ms, steps, 1,
                  "u64+u32", {"workload": name, "n": n, "variant": p["variant"], "algo": algo, "digit_bits": bits,
-                             "num_buckets": B or None}, roof, None, output_matches_stable_library_sort=good)
+                             "num_buckets": B or None}, roof, None, output_matches_stable_library_sort=good,
+                 memory=_memory(8, True, n, algo=algo, digit_bits=bits, num_buckets=B))
 
 
 def run_batched(name, p, args):
@@ -279,7 +296,8 @@ def run_batched(name, p, args):
                  {"workload": name, "arrays": len(offsets) - 1, "keys": int(N), "sizes": "log-uniform [16, 2^20)",
                   "tuned": choice, "tuned_in_this_run": tuned_now},
                  roof, None, per_array_loop={"value": round(N / (ms_loop * 1e-3) / 1e9, 3), "ms": round(ms_loop, 3)},
-                 speedup_vs_per_array_loop=round(ms_loop / ms, 2))
+                 speedup_vs_per_array_loop=round(ms_loop / ms, 2),
+                 memory=_memory(4, False, int(N), len(offsets) - 1, **choice))
 
 
 def serve_trace(I, pool, outbufs, trace, mode, sample_every=0):
