@@ -47,6 +47,10 @@ def _workloads():
             tag = f"radix_r{bits}" if algo == "radix" else f"bucket_B{B}"
             w[f"config3_{v}_u64pairs_100M_{tag}"] = ("pairs", dict(variant=v, n=100_000_000, algo=algo, bits=bits,
                                                                    B=B))
+    for c in range(1, 7):
+        for e in (6, 7, 8):
+            for algo in ("radix", "bucket"):
+                w[f"paper_case{c}_n1e{e}_{algo}"] = ("paper", dict(case=c, n=10 ** e, algo=algo))
     w["config4_batched_10k"] = ("batched", {})
     w["config5_serving"] = ("serving", {})
     return w
@@ -198,6 +202,52 @@ def run_plain(name, p, args):
     return _line(metric, value, "Gkeys/s", ms, args.steps, args.warmup, "u32",
                  {"workload": name, "n": n, "distribution": DISTS[p["dist"]], "algo": algo, "digit_bits": bits,
                   "num_buckets": B or None}, roof, cpu, output_matches_library_sort=ok, memory=mem)
+
+
+# section 4, Table 1 of the paper: seconds on its i5 laptop, one thread, by
+# (case, n) for RADIX sort and bucket sort; context for the case lines only
+PAPER_TABLE1 = {
+    "radix": {1: (1.78, 17.66, 176.84), 2: (1.88, 18.93, 174.85), 3: (1.86, 17.69, 178.68),
+              4: (1.05, 11.10, 105.31), 5: (2.45, 24.56, 246.28), 6: (1.77, 17.66, 176.65)},
+    "bucket": {1: (0.74, 5.84, 45.92), 2: (0.61, 4.14, 26.83), 3: (0.61, 4.12, 28.27),
+               4: (0.31, 3.00, 31.54), 5: (0.78, 8.54, 97.43), 6: (0.61, 5.18, 41.06)},
+}
+
+
+def run_paper(name, p, args):
+    """One of the paper's six input cases at one of its three sizes: radix
+    sort (8-bit digits) or bucket sort with the paper's own map, B = n
+    buckets over the declared range [0, M]."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1206_3511_amd import intsort as I
+
+    case, n, algo = p["case"], p["n"], p["algo"]
+    print(f"bench[{name}]: generating case {case}, n={n}", file=sys.stderr, flush=True)
+    keys_h, M = workloads.paper_case(case, n)
+    keys = torch.from_numpy(keys_h).to("cuda:0")
+    out = torch.empty_like(keys)
+    ctx = I.context(0)
+    opts = dict(algo="radix", digit_bits=8) if algo == "radix" else dict(algo="bucket", num_buckets=n, key_bound=M)
+    fn = lambda: I.sort(keys, out=out, **opts)  # noqa: E731
+    steps = max(2, args.steps // 4)
+    ms = _timed(fn, steps, 1)
+    value = n / (ms * 1e-3) / 1e9
+    avg = _kernel_avgs(ctx, fn, steps)
+    kind = "pass" if algo == "radix" else "bucket_scatter"
+    roof = _roofline("k_onesweep (one pass)" if algo == "radix" else "k_onesweep<BucketDigit> (one scatter pass)",
+                     2 * n * 4, avg.get(kind, float("nan")), {"kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()}})
+    ok = bool(np.array_equal(out.cpu().numpy(), np.sort(keys_h)))
+    sec = PAPER_TABLE1[algo][case][{10**6: 0, 10**7: 1, 10**8: 2}[n]]
+    return _line(f"Gkeys/s (paper case {case}, {algo})", value, "Gkeys/s", ms, steps, 1, "u32",
+                 {"workload": name, "case": case, "n": n, "M": M, "algo": algo,
+                  "buckets": n if algo == "bucket" else None, "declared_range": [0, M] if algo == "bucket" else None},
+                 roof, None, output_matches_library_sort=ok,
+                 paper={"seconds": sec, "Gkeys_per_s": round(n / sec / 1e9, 7),
+                        "machine": "Intel i5 laptop, one thread (section 4)"},
+                 memory=_memory(4, False, n, **opts))
 
 
 def cpu_baseline(keys_h, algo, bits, B, args):
@@ -400,7 +450,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform_u32_100M_radix_r8",
-                    help="one of: " + ", ".join(sorted(WORKLOADS)) + ", or all")
+                    help="one of: " + ", ".join(sorted(WORKLOADS)) + ", all, or paper_suite (the 36 case lines)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="keys of the same input that the CPU oracle sorts (0 = all of them)")
@@ -416,7 +466,12 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    names = sorted(WORKLOADS) if args.workload == "all" else [args.workload]
+    if args.workload == "all":
+        names = sorted(WORKLOADS)
+    elif args.workload == "paper_suite":
+        names = [k for k in WORKLOADS if k.startswith("paper_case")]
+    else:
+        names = [args.workload]
     if args.calibrate_copy:
         calibrate_copy()
     for name in names:
@@ -424,7 +479,8 @@ def main():
             print(f"unknown workload {name}", file=sys.stderr)
             sys.exit(2)
         kind, p = WORKLOADS[name]
-        fn = {"plain": run_plain, "pairs": run_pairs, "batched": run_batched, "serving": run_serving}[kind]
+        fn = {"plain": run_plain, "pairs": run_pairs, "batched": run_batched, "serving": run_serving,
+              "paper": run_paper}[kind]
         print(json.dumps(fn(name, p, args)), flush=True)
         import torch
         torch.cuda.empty_cache()

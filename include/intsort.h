@@ -75,9 +75,15 @@ typedef enum intsort_algo {
  *   digit_bits   radix digit width r: 0 (default 8) | 4 | 8 | 11.  The
  *                number of passes is ceil(key_bits / r) (Algorithm 4's d
  *                for a key of key_bits bits).
- *   num_buckets  bucket sort: number of buckets B, 1..65536 (default 1024
+ *   num_buckets  bucket sort: number of buckets B, 1..2^30 (default 1024
  *                for u32, 65536 for u64).  The bucket of key k is
  *                floor((k - min) * B / (max - min + 1)), exact.
+ *   key_bound    bucket sort: 0 = measure min and max of the keys on the
+ *                device.  Otherwise the caller declares that every key lies
+ *                in [0, key_bound], the bound M of section 2.3, and the
+ *                bucket of k is floor(k * B / (key_bound + 1)); with
+ *                B = n this is Algorithm 2's map.  A key above the bound
+ *                goes to the last bucket, so the output is still sorted.
  *   lds_cutoff   bucket/segmented/batched: segments of at most this many
  *                keys are sorted by one workgroup entirely in LDS, longer
  *                ones by all workgroups together (0 or more than one
@@ -101,6 +107,7 @@ typedef struct intsort_options {
     uint32_t max_passes;
     uint32_t flags;
     uint32_t reserved;
+    uint64_t key_bound;
 } intsort_options;
 
 typedef struct intsort_ctx intsort_ctx;

@@ -54,7 +54,7 @@ def _load(path: str | None = None):
                                      ctypes.POINTER(ctypes.c_int)]
     lib.oracle_radix_lsd.restype = ctypes.c_int
     lib.oracle_bucket.argtypes = [_vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_uint64,
-                                  ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]
+                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]
     lib.oracle_bucket.restype = ctypes.c_int
     lib.oracle_bucket_index.argtypes = [ctypes.c_uint64] * 4
     lib.oracle_bucket_index.restype = ctypes.c_uint64
@@ -137,10 +137,12 @@ class BucketResult:
 
 
 def bucket(keys, vals=None, num_buckets: int = 1024, cutoff: int = 32,
-           want_intermediates: bool = False) -> BucketResult:
+           want_intermediates: bool = False, key_bound: int = 0) -> BucketResult:
     """BUCKET-SORT (Algorithm 2) with the exact bucket map of ``bucket_index``,
     buckets filled in input order and sorted by INSERTION-SORT (Algorithm 1)
-    when they hold at most ``cutoff`` keys, else by a stable merge sort."""
+    when they hold at most ``cutoff`` keys, else by a stable merge sort.
+    ``key_bound`` = M > 0 declares the range [0, M] (section 2.3) instead of
+    the keys' own [min, max]; keys above M join the last bucket."""
     lib = _load()
     keys = _keys(keys)
     n = keys.shape[0]
@@ -156,7 +158,7 @@ def bucket(keys, vals=None, num_buckets: int = 1024, cutoff: int = 32,
         sk = np.zeros(n, dtype=np.uint64)
         sv = None if vals is None else np.zeros(n, dtype=np.uint32)
     _check(lib.oracle_bucket(_ptr(keys), _ptr(out), w, _ptr(vals), _ptr(vout), n,
-                             num_buckets, cutoff, _ptr(mm), _ptr(cnt), _ptr(off), _ptr(sk),
+                             num_buckets, cutoff, key_bound, _ptr(mm), _ptr(cnt), _ptr(off), _ptr(sk),
                              _ptr(sv)))
     return BucketResult(out, vout, int(mm[0]), int(mm[1]), cnt, off,
                         None if sk is None else sk.astype(keys.dtype), sv)

@@ -265,7 +265,10 @@ uint64_t oracle_bucket_index(uint64_t k, uint64_t mn, uint64_t mx, uint64_t B)
  *   nbuckets   : B >= 1.
  *   cutoff     : buckets of at most this many elements use Algorithm 1,
  *                larger ones the stable merge sort.
- *   minmax     : optional [2] -> min, max of the keys (0, 0 for n == 0).
+ *   key_bound  : 0 = the range is the keys' own [min, max]; otherwise the
+ *                range is declared to be [0, key_bound] (the bound M of
+ *                section 2.3), and a key above it goes to the last bucket.
+ *   minmax     : optional [2] -> the range used (0, 0 for n == 0).
  *   counts     : optional [B] bucket sizes.
  *   offsets    : optional [B+1] exclusive prefix of counts (offsets[B] = n).
  *   scat_keys  : optional [n] uint64 keys after the scatter (buckets filled,
@@ -274,7 +277,7 @@ uint64_t oracle_bucket_index(uint64_t k, uint64_t mn, uint64_t mx, uint64_t B)
  */
 int oracle_bucket(const void *keys_in, void *keys_out, int key_bytes,
                   const uint32_t *vals_in, uint32_t *vals_out, uint64_t n,
-                  uint64_t nbuckets, uint64_t cutoff, uint64_t *minmax,
+                  uint64_t nbuckets, uint64_t cutoff, uint64_t key_bound, uint64_t *minmax,
                   uint64_t *counts, uint64_t *offsets, uint64_t *scat_keys,
                   uint32_t *scat_vals)
 {
@@ -300,25 +303,29 @@ int oracle_bucket(const void *keys_in, void *keys_out, int key_bytes,
         return ORACLE_ENOMEM;
     }
 
-    /* value range of the input */
+    /* value range: declared, or that of the input */
     uint64_t mn = 0, mx = 0;
-    if (n > 0) {
+    if (key_bound) {
+        mx = key_bound;
+    } else if (n > 0) {
         mn = A[0]; mx = A[0];
         for (uint64_t i = 1; i < n; i++) {
             if (A[i] < mn) mn = A[i];
             if (A[i] > mx) mx = A[i];
         }
     }
+    /* keys above a declared bound join the last bucket */
+#define BUCKET(k) (((k) > mx) ? nbuckets - 1 : bucket_of((k), mn, mx, nbuckets))
 
     /* bucket sizes, then where each bucket starts in the concatenation */
-    for (uint64_t i = 0; i < n; i++) cnt[bucket_of(A[i], mn, mx, nbuckets)] += 1;
+    for (uint64_t i = 0; i < n; i++) cnt[BUCKET(A[i])] += 1;
     off[0] = 0;
     for (uint64_t b = 0; b < nbuckets; b++) off[b + 1] = off[b] + cnt[b];
 
     /* insert every element into its bucket in input order */
     for (uint64_t b = 0; b < nbuckets; b++) next[b] = off[b];
     for (uint64_t i = 0; i < n; i++) {
-        uint64_t b = bucket_of(A[i], mn, mx, nbuckets);
+        uint64_t b = BUCKET(A[i]);
         S[next[b]] = A[i];
         if (vals_in) SV[next[b]] = vals_in[i];
         next[b] += 1;
@@ -342,6 +349,7 @@ int oracle_bucket(const void *keys_in, void *keys_out, int key_bytes,
     if (offsets) memcpy(offsets, off, (nbuckets + 1) * sizeof(uint64_t));
     free(A); free(S); free(T); free(cnt); free(off); free(next);
     free(SV); free(TV);
+#undef BUCKET
     return ORACLE_OK;
 }
 
@@ -378,7 +386,7 @@ int oracle_segmented(const void *keys_in, void *keys_out, int key_bytes,
                                   NULL, NULL, NULL);
         else
             rc = oracle_bucket(kin, kout, key_bytes, vin, vout, m, nbuckets,
-                               cutoff, NULL, NULL, NULL, NULL, NULL);
+                               cutoff, 0, NULL, NULL, NULL, NULL, NULL);
         if (rc != ORACLE_OK) return rc;
     }
     return ORACLE_OK;

@@ -39,6 +39,9 @@ intsort_status read_opts(const intsort_options *in, intsort_key_type kt, intsort
     if (out->num_buckets == 0) out->num_buckets = kt == INTSORT_U64 ? 65536u : 1024u;
     if (out->num_buckets > MAX_BUCKETS) return INTSORT_ERR_UNSUPPORTED;
     if (out->flags & ~INTSORT_FLAG_NO_PASS_SKIP) return INTSORT_ERR_INVALID_ARGUMENT;
+    // a declared bound beyond the key width says nothing a measured range
+    // would not, and 32-bit keys compute their bucket with 32-bit ranges
+    if (kt == INTSORT_U32 && out->key_bound > 0xffffffffull) return INTSORT_ERR_INVALID_ARGUMENT;
     return INTSORT_OK;
 }
 

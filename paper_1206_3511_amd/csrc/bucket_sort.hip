@@ -8,11 +8,15 @@
 //   3. offsets: where every bucket starts in the concatenation (exclusive
 //      scan of the histogram) -- concatenation costs no data movement;
 //   4. a stable scatter by b(k): keys keep their input order inside each
-//      bucket, as the paper's lists do.  B <= 2048 takes one pass whose digit
-//      is b(k) itself; up to 65536 buckets take two stable 8-bit passes over
-//      b(k), after which the bucket starts are found where b changes;
-//   5. every bucket is sorted on its own by the segmented sort (buckets that
-//      fit on chip by one workgroup in LDS, larger ones by all workgroups).
+//      bucket, as the paper's lists do.  It takes one stable 8-bit pass per
+//      byte of b(k) (1 to 4); with more than 16384 buckets the bucket starts
+//      are then found where b changes;
+//   5. every bucket is sorted on its own by the segmented sort (on chip up
+//      to one workgroup's capacity, by all workgroups above).  Buckets are
+//      value ranges in order, so sorting a run of whole buckets by key sorts
+//      each of them: with many tiny buckets (the paper's B = n) the small
+//      ones are sorted in windows of consecutive buckets instead, one
+//      workgroup in LDS each.
 // Every step keeps its data on the device; the host never waits.
 
 #include <stdint.h>
@@ -23,30 +27,42 @@
 #include "device_common.hpp"
 #include "intsort.h"
 #include "internal.hpp"
+#include "lds_sort.hpp"
 #include "onesweep.hpp"
 #include "sort_plans.hpp"
 
 namespace intsort {
 
 constexpr int BK_THREADS = 256;
-constexpr uint32_t SUBHIST_WORDS = 2 * 256;
+constexpr uint32_t SUBHIST_WORDS = 4 * 256;
+constexpr uint32_t SUFFIX_CHUNK = 4096;   // offsets per workgroup of the suffix minimum
+constexpr uint64_t WINDOW_AVG = 64;       // below this many keys per bucket, windows
 
-// counts of the low and the high byte of b(k), for the two scatter passes
+// counts of every byte of b(k) that a scatter pass sorts on
 template <typename K>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restrict__ keys, uint64_t n,
                                                                const uint64_t *__restrict__ minmax, uint32_t B,
-                                                               uint32_t *__restrict__ subhist)
+                                                               uint32_t passes, uint32_t *__restrict__ subhist)
 {
     __shared__ uint32_t s_h[SUBHIST_WORDS];
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS) s_h[i] = 0;
     __syncthreads();
+    auto count = [&](K k) {
+        const uint32_t b = bucket_of(m, k);
+        for (uint32_t p = 0; p < passes; p++) lds_count(s_h + p * 256, (b >> (8 * p)) & 255u);
+    };
+    constexpr int KPV = 16 / (int)sizeof(K);
+    struct alignas(16) Vec { K v[KPV]; };
+    const uint64_t nvec = n / KPV;
+    const Vec *vk = reinterpret_cast<const Vec *>(keys);
     const uint64_t stride = (uint64_t)gridDim.x * BK_THREADS;
-    for (uint64_t i = (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; i < n; i += stride) {
-        const uint32_t b = bucket_of(m, keys[i]);
-        atomicAdd(&s_h[b & 255u], 1u);
-        atomicAdd(&s_h[256 + (b >> 8)], 1u);
+    for (uint64_t v = (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; v < nvec; v += stride) {
+        const Vec x = vk[v];
+#pragma unroll
+        for (int e = 0; e < KPV; e++) count(x.v[e]);
     }
+    for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; i < n; i += stride) count(keys[i]);
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS)
         if (s_h[i]) atomicAdd(&subhist[i], s_h[i]);
@@ -109,13 +125,13 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
         a.excl[p * a.radix + d] = ex;
     }
     if (tid == 0) {
-        uint32_t *w = a.plan;
-        if (a.passes == 1) {
-            w[0] = 1; w[1] = BUF_IN; w[2] = BUF_OUT; w[3] = 0;
-        } else {
-            w[0] = 1; w[1] = BUF_IN; w[2] = BUF_TMP; w[3] = 0;
-            w += PLAN_WORDS;
-            w[0] = 1; w[1] = BUF_TMP; w[2] = BUF_OUT; w[3] = 1;
+        // passes alternate so that the last one lands in the output
+        uint32_t prev = BUF_IN;
+        for (uint32_t q = 0; q < a.passes; q++) {
+            uint32_t *w = a.plan + q * PLAN_WORDS;
+            const uint32_t dst = ((a.passes - 1 - q) % 2 == 0) ? BUF_OUT : BUF_TMP;
+            w[0] = 1; w[1] = prev; w[2] = dst; w[3] = q;
+            prev = dst;
         }
     }
 }
@@ -135,33 +151,134 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_bounds(const K *__restric
     }
 }
 
-// an empty bucket starts where the next nonempty one does: offsets[b] =
-// min(offsets[b], offsets[b + 1]) from the end (one workgroup)
-__global__ __launch_bounds__(1024) void k_suffix_min(uint64_t *offsets, uint32_t count)
+// An empty bucket starts where the next nonempty one does: offsets[b] =
+// min(offsets[b], offsets[b + 1], ...).  Three launches: the minimum of
+// every chunk of SUFFIX_CHUNK offsets, the minimum over the chunks after each
+// chunk, then the suffix minimum inside every chunk.
+__global__ __launch_bounds__(BK_THREADS) void k_suffix_min_chunks(const uint64_t *offsets, uint32_t count,
+                                                                  uint64_t *cmin)
+{
+    __shared__ uint64_t s_m[BK_THREADS];
+    const uint64_t lo = (uint64_t)blockIdx.x * SUFFIX_CHUNK;
+    uint64_t m = ~0ull;
+    for (uint64_t i = lo + threadIdx.x; i < min((uint64_t)count, lo + SUFFIX_CHUNK); i += BK_THREADS)
+        m = min(m, offsets[i]);
+    s_m[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = BK_THREADS / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s_m[threadIdx.x] = min(s_m[threadIdx.x], s_m[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cmin[blockIdx.x] = s_m[0];
+}
+
+// one workgroup: cmin[c] becomes the minimum over the chunks after c
+__global__ __launch_bounds__(1024) void k_suffix_min_carry(uint64_t *cmin, uint32_t chunks)
 {
     __shared__ uint64_t s_m[1024];
     const uint32_t tid = threadIdx.x;
-    const uint32_t per = (count + 1023) / 1024;
-    const uint32_t lo = tid * per, hi = min(count, lo + per);
+    const uint32_t per = (chunks + 1023) / 1024;
+    const uint32_t lo = tid * per, hi = min(chunks, lo + per);
     uint64_t run = ~0ull;
-    for (uint32_t i = hi; i-- > lo;) run = min(run, offsets[i]);
+    for (uint32_t i = lo; i < hi; i++) run = min(run, cmin[i]);
     s_m[tid] = run;
     __syncthreads();
     if (tid == 0) {
         uint64_t r = ~0ull;
         for (int t = 1023; t >= 0; t--) {
             const uint64_t x = s_m[t];
-            s_m[t] = r;   // minimum over the chunks after t
+            s_m[t] = r;   // minimum over the threads after t
             r = min(r, x);
         }
     }
     __syncthreads();
     run = s_m[tid];
     for (uint32_t i = hi; i-- > lo;) {
+        const uint64_t x = cmin[i];
+        cmin[i] = run;
+        run = min(run, x);
+    }
+}
+
+__global__ __launch_bounds__(BK_THREADS) void k_suffix_min_apply(uint64_t *offsets, uint32_t count,
+                                                                 const uint64_t *carry)
+{
+    constexpr uint32_t PER = SUFFIX_CHUNK / BK_THREADS;
+    __shared__ uint64_t s_m[BK_THREADS];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t lo = (uint64_t)blockIdx.x * SUFFIX_CHUNK + (uint64_t)tid * PER;
+    const uint64_t hi = min((uint64_t)count, lo + PER);
+    uint64_t m = ~0ull;
+    for (uint64_t i = lo; i < hi; i++) m = min(m, offsets[i]);
+    s_m[tid] = m;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t r = carry[blockIdx.x];
+        for (int t = BK_THREADS - 1; t >= 0; t--) {
+            const uint64_t x = s_m[t];
+            s_m[t] = r;   // minimum over everything after thread t's offsets
+            r = min(r, x);
+        }
+    }
+    __syncthreads();
+    uint64_t run = s_m[tid];
+    for (uint64_t i = hi; i-- > lo;) {
         run = min(run, offsets[i]);
         offsets[i] = run;
     }
 }
+
+// the declared range [0, key_bound] in place of a measured one
+__global__ void k_set_range(uint64_t *minmax, uint64_t lo, uint64_t hi)
+{
+    minmax[0] = lo;
+    minmax[1] = hi;
+}
+
+// Windows of consecutive small buckets.  Window g holds the buckets that
+// start in positions [g*half, (g+1)*half) of the scattered array, less a
+// last bucket longer than half (that one goes to the segmented sort).  A
+// bucket start is found from the key at a position: the bucket b of the key
+// at p starts at offsets[b]; the first bucket starting at or after p starts
+// at p if offsets[b] == p, else at offsets[b + 1].  A window holds at most
+// half + half keys.
+template <typename K>
+struct WindowSrc {
+    const K *keys;              // scattered keys, grouped by bucket
+    K *out;
+    const uint32_t *vin;
+    uint32_t *vout;
+    const uint64_t *offsets;    // [B + 1], nondecreasing
+    const uint64_t *minmax;
+    uint32_t B;
+    uint32_t half;
+    uint64_t n;
+    __device__ __forceinline__ uint64_t start_at_or_after(const BucketMap &m, uint64_t p) const
+    {
+        if (p >= n) return n;
+        const uint32_t b = bucket_of(m, keys[p]);
+        const uint64_t s = offsets[b];
+        return s == p ? p : offsets[b + 1];
+    }
+    template <typename KK>
+    __device__ __forceinline__ void seg(uint64_t g, const KK *&kin, KK *&kout, const uint32_t *&vi, uint32_t *&vo,
+                                        uint32_t &mlen, uint32_t &base) const
+    {
+        const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
+        const uint64_t lo = start_at_or_after(m, g * half);
+        uint64_t hi = start_at_or_after(m, (g + 1) * half);
+        if (hi > lo) {
+            const uint64_t sl = offsets[bucket_of(m, keys[hi - 1])];
+            if (hi - sl > half) hi = sl > lo ? sl : lo;
+        }
+        mlen = hi > lo ? (uint32_t)(hi - lo) : 0u;
+        base = (uint32_t)lo;
+        kin = reinterpret_cast<const KK *>(keys) + lo;
+        kout = reinterpret_cast<KK *>(out) + lo;
+        vi = vin ? vin + lo : nullptr;
+        vo = vout ? vout + lo : nullptr;
+    }
+};
 
 // ------------------------------------------------------------------ host
 
@@ -176,7 +293,9 @@ BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_
     BucketLayout L{};
     L.buckets = o.num_buckets;
     L.bits = scatter_bits(L.buckets);
-    L.scatter_passes = L.buckets <= 256 ? 1u : 2u;
+    // one 8-bit pass per byte of the largest bucket index
+    L.scatter_passes = 1;
+    while (L.scatter_passes < 4 && ((uint64_t)(L.buckets - 1) >> (8 * L.scatter_passes)) != 0) L.scatter_passes++;
     const uint64_t tile = key_bytes == 4 ? scatter_tile<uint32_t>(L.bits) : scatter_tile<uint64_t>(L.bits);
     L.num_tiles = (n + tile - 1) / tile;
     const uint64_t radix = 1ull << L.bits;
@@ -185,10 +304,11 @@ BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_
     L.counters = take((size_t)CTR_WORDS * 4);
     L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
     L.minmax = take(16);
-    L.counts = take((size_t)L.buckets * 4);
+    L.counts = take(L.buckets <= BUCKET_LDS_HIST_MAX ? (size_t)L.buckets * 4 : 0);
     L.subhist = take((size_t)SUBHIST_WORDS * 4);
-    L.excl = take((size_t)2 * radix * 4);
+    L.excl = take((size_t)L.scatter_passes * radix * 4);
     L.offsets = take((size_t)(L.buckets + 1) * 8);
+    L.suffix = take((size_t)((L.buckets + 1 + SUFFIX_CHUNK - 1) / SUFFIX_CHUNK) * 8);
     L.status0 = take((size_t)L.num_tiles * (radix + 1) * 4);
     L.status1 = take((size_t)L.num_tiles * (radix + 1) * 4);
     L.tmpb_keys = take(n * (size_t)key_bytes);
@@ -230,17 +350,19 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
 
     if (tm) tm->start(s);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, counters, (uint64_t)CTR_WORDS, 0u);
-    hipError_t e = minmax_run((int)sizeof(K), c.keys_in, c.n, minmax, s);
+    hipError_t e = hipSuccess;
+    if (c.opts.key_bound) hipLaunchKernelGGL(k_set_range, dim3(1), dim3(1), 0, s, minmax, 0ull, c.opts.key_bound);
+    else e = minmax_run((int)sizeof(K), c.keys_in, c.n, minmax, s);
     if (e != hipSuccess) return e;
     if (tm) tm->mark(INTSORT_KERNEL_MINMAX, 0, s);
     const bool full_hist = B <= BUCKET_LDS_HIST_MAX;
     if (full_hist) {
         e = bucket_histogram_run((int)sizeof(K), c.keys_in, c.n, minmax, B, counts, s);
     } else {
-        hipLaunchKernelGGL(k_fill<uint32_t>, dim3(2), dim3(256), 0, s, subhist, (uint64_t)SUBHIST_WORDS, 0u);
+        hipLaunchKernelGGL(k_fill<uint32_t>, dim3(4), dim3(256), 0, s, subhist, (uint64_t)SUBHIST_WORDS, 0u);
         uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
         hipLaunchKernelGGL((k_bucket_subhist<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
-                           s, static_cast<const K *>(c.keys_in), c.n, minmax, B, subhist);
+                           s, static_cast<const K *>(c.keys_in), c.n, minmax, B, L.scatter_passes, subhist);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -283,11 +405,32 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
         uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
         hipLaunchKernelGGL((k_bucket_bounds<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
                            s, tmpb, c.n, minmax, B, offsets);
-        hipLaunchKernelGGL(k_suffix_min, dim3(1), dim3(1024), 0, s, offsets, B + 1);
+        uint64_t *cmin = reinterpret_cast<uint64_t *>(ws + L.suffix);
+        const uint32_t chunks = (B + 1 + SUFFIX_CHUNK - 1) / SUFFIX_CHUNK;
+        hipLaunchKernelGGL(k_suffix_min_chunks, dim3(chunks), dim3(BK_THREADS), 0, s, offsets, B + 1, cmin);
+        hipLaunchKernelGGL(k_suffix_min_carry, dim3(1), dim3(1024), 0, s, cmin, chunks);
+        hipLaunchKernelGGL(k_suffix_min_apply, dim3(chunks), dim3(BK_THREADS), 0, s, offsets, B + 1, cmin);
         if (tm) tm->mark(INTSORT_KERNEL_PLAN, 1, s);
     }
 
-    // every bucket sorted on its own: buckets are the segments
+    // every bucket sorted on its own.  With many tiny buckets (fewer than
+    // WINDOW_AVG keys each on average) the small ones go in windows of whole
+    // consecutive buckets, one workgroup in LDS each, and only the rest are
+    // segments; otherwise every bucket is a segment of its own size class.
+    using CL = SegClasses<K>;
+    constexpr uint32_t HALF = CL::LDS_MAX / 2;
+    const bool windows = c.n < (uint64_t)B * WINDOW_AVG;
+    if (windows) {
+        LdsSortArgs<WindowSrc<K>> la{};
+        la.src = WindowSrc<K>{tmpb, static_cast<K *>(c.keys_out), PAIRS ? tmpb_v : nullptr,
+                              PAIRS ? c.vals_out : nullptr, offsets, minmax, B, HALF, c.n};
+        la.list = nullptr;
+        la.direct_count = (uint32_t)((c.n + HALF - 1) / HALF);
+        hipLaunchKernelGGL((k_lds_sort<K, PAIRS, 512, CL::LDS_MAX / 512, WindowSrc<K>>), dim3(la.direct_count),
+                           dim3(512), 0, s, la);
+        if (tm) tm->mark(INTSORT_KERNEL_SEGMENT_SORT, 1, s);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     SegCall sc{};
     sc.keys_in = tmpb;
     sc.keys_out = c.keys_out;
@@ -303,6 +446,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     sc.L = L.S;
     sc.ws = segws;
     sc.timer = tm;
+    sc.min_size = windows ? HALF : 0u;   // the windows took these
     return segmented_sort_run(sc, s);
 }
 

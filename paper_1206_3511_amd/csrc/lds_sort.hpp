@@ -18,6 +18,17 @@
 
 namespace intsort {
 
+// size classes of the on-chip sort: the capacity of one workgroup each
+template <typename K>
+struct SegClasses {
+    static constexpr int NCLASS = 4;
+    static constexpr uint32_t CAP0 = 64 * 4;       // one wave
+    static constexpr uint32_t CAP1 = 256 * 8;
+    static constexpr uint32_t CAP2 = 512 * 16;
+    static constexpr uint32_t CAP3 = sizeof(K) == 4 ? 512 * 32 : 512 * 16;
+    static constexpr uint32_t LDS_MAX = CAP3;      // above: the multi-workgroup path
+};
+
 // where the keys of segment s live: one packed array cut by offsets ...
 struct PackedSrc {
     const void *in;
@@ -59,8 +70,9 @@ struct DescSrc {
 template <class Src>
 struct LdsSortArgs {
     Src src;
-    const uint32_t *list;        // segment ids of this size class
+    const uint32_t *list;        // segment ids of this size class, or null:
     const uint32_t *list_count;  // device count of listed segments
+    uint32_t direct_count;       // without a list, segments 0 .. direct_count-1
 };
 
 template <typename K, bool PAIRS, int NT, int IPT, class Src>
@@ -82,8 +94,14 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
     K *s_stage = reinterpret_cast<K *>(s_raw);
     uint64_t *s_bits = reinterpret_cast<uint64_t *>(s_raw);
 
-    if (blockIdx.x >= *a.list_count) return;
-    const uint32_t seg = a.list[blockIdx.x];
+    uint32_t seg;
+    if (a.list) {
+        if (blockIdx.x >= *a.list_count) return;
+        seg = a.list[blockIdx.x];
+    } else {
+        if (blockIdx.x >= a.direct_count) return;
+        seg = blockIdx.x;
+    }
     const K *kin;
     K *kout;
     const uint32_t *vin;

@@ -32,17 +32,6 @@
 
 namespace intsort {
 
-// size classes of the segmented sort: capacity of one workgroup each
-template <typename K>
-struct SegClasses {
-    static constexpr int NCLASS = 4;
-    static constexpr uint32_t CAP0 = 64 * 4;       // one wave
-    static constexpr uint32_t CAP1 = 256 * 8;
-    static constexpr uint32_t CAP2 = 512 * 16;
-    static constexpr uint32_t CAP3 = sizeof(K) == 4 ? 512 * 32 : 512 * 16;
-    static constexpr uint32_t LDS_MAX = CAP3;      // above: the multi-workgroup path
-};
-
 constexpr int SEG_HIST_THREADS = 256;
 
 struct SegWs {
@@ -64,6 +53,7 @@ struct SegWs {
     uint32_t lds_cutoff;      // longer segments take the multi-workgroup path
     uint32_t *slot_mask;      // [slot_cap] digit passes each large segment runs
     uint32_t skip;            // leave out passes whose digit is constant in the segment
+    uint32_t min_size;        // segments of at most this many keys are left alone
 };
 
 // One thread per segment: classify by size; a large segment reserves a run
@@ -95,7 +85,8 @@ __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segm
     int cls = -1;
     if (s < num_segments) {
         src.template seg<K>(s, kin, kout, vin, vout, m, lo);
-        if (m > w.lds_cutoff) cls = 4;
+        if (m <= w.min_size) cls = -1;
+        else if (m > w.lds_cutoff) cls = 4;
         else if (m <= CL::CAP0) cls = 0;
         else if (m <= CL::CAP1) cls = 1;
         else if (m <= CL::CAP2) cls = 2;
@@ -332,6 +323,7 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     w.lds_cutoff = L.lds_cutoff;
     w.slot_mask = reinterpret_cast<uint32_t *>(ws + L.slot_mask);
     w.skip = (c.opts.flags & INTSORT_FLAG_NO_PASS_SKIP) ? 0u : 1u;
+    w.min_size = c.min_size;
 
     if (tm) tm->start(s);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, w.counters, (uint64_t)CTR_WORDS, 0u);
@@ -344,26 +336,28 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     LdsSortArgs<Src> la{};
     la.src = src;
     const uint64_t S = c.num_segments;
-    auto grid_for = [&](uint32_t lo_exclusive) {
+    auto grid_for = [&](uint32_t lo_exclusive, uint32_t cap) {
         // at most this many segments can be longer than lo_exclusive; none
-        // longer than the cutoff reaches an on-chip class
-        if (lo_exclusive >= L.lds_cutoff) return 0u;
+        // longer than the cutoff, and none up to min_size, reaches an
+        // on-chip class
+        if (lo_exclusive >= L.lds_cutoff || cap <= c.min_size) return 0u;
+        lo_exclusive = std::max(lo_exclusive, c.min_size);
         const uint64_t by_n = c.n / (uint64_t)(lo_exclusive + 1);
         return (uint32_t)std::min<uint64_t>(S, lo_exclusive == 0 ? S : by_n);
     };
     la.list = w.lists + 0 * L.list_stride;
     la.list_count = w.counters + CTR_SEG_CLASS + 0;
-    launch_lds_class<K, PAIRS, 64, 4>(la, grid_for(0), s);
+    launch_lds_class<K, PAIRS, 64, 4>(la, grid_for(0, CL::CAP0), s);
     la.list = w.lists + 1 * L.list_stride;
     la.list_count = w.counters + CTR_SEG_CLASS + 1;
-    launch_lds_class<K, PAIRS, 256, 8>(la, grid_for(CL::CAP0), s);
+    launch_lds_class<K, PAIRS, 256, 8>(la, grid_for(CL::CAP0, CL::CAP1), s);
     la.list = w.lists + 2 * L.list_stride;
     la.list_count = w.counters + CTR_SEG_CLASS + 2;
-    launch_lds_class<K, PAIRS, 512, 16>(la, grid_for(CL::CAP1), s);
+    launch_lds_class<K, PAIRS, 512, 16>(la, grid_for(CL::CAP1, CL::CAP2), s);
     if (CL::CAP3 > CL::CAP2) {
         la.list = w.lists + 3 * L.list_stride;
         la.list_count = w.counters + CTR_SEG_CLASS + 3;
-        launch_lds_class<K, PAIRS, 512, (CL::CAP3 > CL::CAP2 ? 32 : 16)>(la, grid_for(CL::CAP2), s);
+        launch_lds_class<K, PAIRS, 512, (CL::CAP3 > CL::CAP2 ? 32 : 16)>(la, grid_for(CL::CAP2, CL::CAP3), s);
     }
     if (tm) tm->mark(INTSORT_KERNEL_SEGMENT_SORT, 0, s);
     hipError_t e = hipGetLastError();

@@ -10,7 +10,7 @@
 
 namespace intsort {
 
-constexpr uint32_t MAX_BUCKETS = 1u << 16;
+constexpr uint32_t MAX_BUCKETS = 1u << 30;
 constexpr uint64_t MAX_SEGMENTS = 1ull << 24;
 
 struct SegLayout {
@@ -21,7 +21,8 @@ struct SegLayout {
 };
 
 struct BucketLayout {
-    size_t counters, plan, minmax, counts, subhist, excl, offsets, status0, status1, tmpb_keys, tmpb_vals, seg, total;
+    size_t counters, plan, minmax, counts, subhist, excl, offsets, suffix, status0, status1, tmpb_keys, tmpb_vals,
+        seg, total;
     uint32_t buckets, bits, scatter_passes;
     uint64_t num_tiles;
     SegLayout S;
@@ -60,6 +61,7 @@ struct SegCall {
     SegLayout L;
     char *ws;
     Timer *timer;
+    uint32_t min_size;   // segments of at most this many keys are left as they are
 };
 
 SegLayout segmented_layout(int key_bytes, bool pairs, uint64_t n, uint64_t num_segments,

@@ -58,7 +58,8 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("algo", ctypes.c_uint32),
                 ("digit_bits", ctypes.c_uint32), ("num_buckets", ctypes.c_uint32),
                 ("lds_cutoff", ctypes.c_uint32), ("max_passes", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("key_bound", ctypes.c_uint64)]
 
 
 _lib = None
@@ -131,7 +132,8 @@ def _check(rc: int, where: str):
 
 
 def make_options(algo: str | int = "radix", digit_bits: int = 0, num_buckets: int = 0,
-                 lds_cutoff: int = 0, max_passes: int = 0, skip_passes: bool = True) -> Options:
+                 lds_cutoff: int = 0, max_passes: int = 0, skip_passes: bool = True,
+                 key_bound: int = 0) -> Options:
     o = Options()
     lib().intsort_default_options(ctypes.byref(o))
     o.algo = algo if isinstance(algo, int) else {"radix": RADIX, "bucket": BUCKET}[algo]
@@ -140,6 +142,7 @@ def make_options(algo: str | int = "radix", digit_bits: int = 0, num_buckets: in
     o.lds_cutoff = lds_cutoff
     o.max_passes = max_passes
     o.flags = 0 if skip_passes else FLAG_NO_PASS_SKIP
+    o.key_bound = key_bound
     return o
 
 

@@ -18,6 +18,7 @@ def main():
     for v in ("full", "b40"):
         k, _ = w.config3_pairs(v, 1 << 16)
         out["config3"][v] = hex(w.checksum(k))
+    out["paper_cases"] = {str(c): hex(w.checksum(w.paper_case(c, 1 << 16)[0])) for c in range(1, 7)}
     sizes, dists = w.segment_plan(64)
     out["segment_plan_64"] = {"sizes": [int(x) for x in sizes], "dists": [int(x) for x in dists]}
     with open(os.path.join(HERE, "input_checksums.json"), "w") as f:

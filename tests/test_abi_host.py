@@ -71,6 +71,12 @@ def test_validation_order_on_planning_context(plan_ctx):
     assert _call_sort(plan_ctx, opts=bad) == I.ERR_INVALID_ARGUMENT
     # more keys than a 30-bit status word can count
     assert _call_sort(plan_ctx, kout=1 << 40, n=1 << 31, wsb=1 << 62) == I.ERR_UNSUPPORTED
+    # bucket counts up to 2^30; a declared range must fit the key width
+    assert _call_sort(plan_ctx, wsb=1 << 62, opts=I.make_options("bucket", num_buckets=1 << 30)) == I.ERR_UNSUPPORTED
+    assert _call_sort(plan_ctx, opts=I.make_options("bucket", num_buckets=(1 << 30) + 1)) == I.ERR_UNSUPPORTED
+    assert _call_sort(plan_ctx, opts=I.make_options("bucket", key_bound=1 << 32)) == I.ERR_INVALID_ARGUMENT
+    assert _call_sort(plan_ctx, opts=I.make_options("bucket", key_bound=(1 << 32) - 1)) == I.ERR_UNSUPPORTED
+    assert _call_sort(plan_ctx, kt=I.U64, opts=I.make_options("bucket", key_bound=1 << 40)) == I.ERR_UNSUPPORTED
 
 
 def test_pairs_validation(plan_ctx):

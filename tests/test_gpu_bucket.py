@@ -86,3 +86,65 @@ def test_config2_bucket_full_size(dist):
     out = host(I.sort(dev(keys), algo="bucket", num_buckets=1024))
     np.testing.assert_array_equal(out, oracle.radix_lsd(keys).keys)
     assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("B,n", [(70_000, 65_537), (100_000, 300_007), ((1 << 24) + 5, 1 << 21)])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_bucket_three_and_four_byte_indices(B, n, dtype):
+    """More than 65536 buckets take three or four 8-bit scatter passes: the
+    scattered array and the sorted pairs equal the oracle's."""
+    print(f"bucket B={B} n={n} {np.dtype(dtype).name}", flush=True)
+    keys = rand_keys(np.random.default_rng(B + n), n, dtype)
+    vals = np.arange(n, dtype=np.uint32)
+    ref = oracle.bucket(keys, vals, num_buckets=B, want_intermediates=True)
+    sk, sv = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=B, max_passes=1)
+    np.testing.assert_array_equal(host(sk), ref.scat_keys)
+    np.testing.assert_array_equal(host(sv), ref.scat_vals)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=B)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+    assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("case", range(1, 7))
+@pytest.mark.parametrize("n", [100_003, 1_000_000])
+def test_paper_map_with_declared_bound(case, n):
+    """Section 4's cases sorted with section 2.3's map: B = n buckets and the
+    declared range [0, M], b(k) = floor(n*k/(M+1)).  The scatter and the
+    sorted pairs equal the oracle's under the same declared range."""
+    keys, M = workloads.paper_case(case, n)
+    print(f"paper case {case} n={n} M={M}", flush=True)
+    vals = np.arange(n, dtype=np.uint32)
+    ref = oracle.bucket(keys, vals, num_buckets=n, key_bound=M, want_intermediates=True)
+    sk, sv = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=n, key_bound=M, max_passes=1)
+    np.testing.assert_array_equal(host(sk), ref.scat_keys)
+    np.testing.assert_array_equal(host(sv), ref.scat_vals)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=n, key_bound=M)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+    out = I.sort(dev(keys), algo="bucket", num_buckets=n, key_bound=M)
+    np.testing.assert_array_equal(host(out), ref.keys)
+    assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_windows_and_large_buckets_mixed(dtype):
+    """Small buckets go through windows of whole consecutive buckets, buckets
+    above half a workgroup's capacity through the segmented sort: a mix of
+    a few huge runs of equal or close keys with many small buckets."""
+    rng = np.random.default_rng(11)
+    n = 1_500_000
+    parts = [rng.integers(0, 1 << 30, n // 2, dtype=np.uint64),
+             np.full(n // 6, 12345, dtype=np.uint64),
+             rng.integers(1 << 29, (1 << 29) + 20_000, n // 6, dtype=np.uint64)]
+    parts.append(rng.integers(0, 1 << 30, n - sum(len(p) for p in parts), dtype=np.uint64))
+    keys = np.concatenate(parts)
+    rng.shuffle(keys)
+    keys = keys.astype(dtype)
+    vals = np.arange(n, dtype=np.uint32)
+    for B in (4096, 65536, 300_000):
+        ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=B)
+        ref = oracle.radix_lsd(keys, vals)
+        np.testing.assert_array_equal(host(ok), ref.keys)
+        np.testing.assert_array_equal(host(ov), ref.vals)
+    assert I.device_error(0) == 0

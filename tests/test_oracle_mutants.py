@@ -31,8 +31,10 @@ MUTANTS = [
     ("bucket map in 64-bit arithmetic",
      "u128 num = (u128)(k - mn) * (u128)B;", "u128 num = (u128)((k - mn) * B);"),
     ("buckets filled last-to-first",
-     "for (uint64_t i = 0; i < n; i++) {\n        uint64_t b = bucket_of(A[i], mn, mx, nbuckets);",
-     "for (uint64_t i = n; i-- > 0;) {\n        uint64_t b = bucket_of(A[i], mn, mx, nbuckets);"),
+     "for (uint64_t i = 0; i < n; i++) {\n        uint64_t b = BUCKET(A[i]);",
+     "for (uint64_t i = n; i-- > 0;) {\n        uint64_t b = BUCKET(A[i]);"),
+    ("declared range ignored",
+     "if (key_bound) {", "if (0) {"),
     ("min taken as the first key",
      "if (A[i] < mn) mn = A[i];", "if (0) mn = A[i];"),
     ("payload not moved in the digit sort",
@@ -85,6 +87,11 @@ CHECK = textwrap.dedent(r'''
     b = np.array([(int(x) - mn) * 64 // (mxx - mn + 1) for x in k])
     ok &= (res.kmin, res.kmax) == (mn, mxx)
     ok &= np.array_equal(res.scat_keys, k[np.argsort(b, kind="stable")])
+    # declared range [0, M] with B = n: the map floor(n*k/(M+1))
+    kk = rng.integers(0, 10**6 + 1, 3000, dtype=np.uint64).astype(np.uint32)
+    res = oracle.bucket(kk, num_buckets=3000, key_bound=10**6, want_intermediates=True)
+    want = np.bincount([(3000 * int(x)) // (10**6 + 1) for x in kk], minlength=3000)
+    ok &= np.array_equal(res.counts.astype(np.int64), want)
     sys.exit(0 if ok else 3)
 ''')
 

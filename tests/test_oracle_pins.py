@@ -253,3 +253,38 @@ def test_segmented_rejects_bad_offsets():
         oracle.segmented(keys, np.array([0, 6, 4, 10], dtype=np.uint64))
     with pytest.raises(RuntimeError):
         oracle.segmented(keys, np.array([0, 4, 9], dtype=np.uint64))
+
+
+# ---- declared range: the bound M of section 2.3 and the map with B = n
+
+
+@pytest.mark.parametrize("M,n", [(10**4, 5000), (10**6, 20_000), (10**8, 3000), (7, 100)])
+def test_bucket_declared_bound_paper_map(M, n):
+    """With B = n buckets and the range declared as [0, M], the bucket of k
+    is floor(n*k/(M+1)) (checked with Python integers), every bucket holds
+    its keys in input order, and the result is the library's stable sort."""
+    rng = np.random.default_rng(M + n)
+    keys = rng.integers(0, M + 1, size=n, dtype=np.uint64).astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint32)
+    r = oracle.bucket(keys, vals, num_buckets=n, key_bound=M, want_intermediates=True)
+    assert (r.kmin, r.kmax) == (0, M)
+    want = np.zeros(n, dtype=np.uint64)
+    for k in keys.tolist():
+        want[(n * k) // (M + 1)] += 1
+    np.testing.assert_array_equal(r.counts, want)
+    b = np.array([(n * k) // (M + 1) for k in keys.tolist()], dtype=np.int64)
+    order = np.argsort(b, kind="stable")
+    np.testing.assert_array_equal(r.scat_keys, keys[order])
+    np.testing.assert_array_equal(r.scat_vals, vals[order])
+    o = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(r.keys, keys[o])
+    np.testing.assert_array_equal(r.vals, vals[o])
+
+
+def test_bucket_keys_above_declared_bound_join_last_bucket():
+    keys = np.array([5, 100, 3, 1000, 7, 2**32 - 1, 50], dtype=np.uint32)
+    r = oracle.bucket(keys, num_buckets=4, key_bound=99, want_intermediates=True)
+    np.testing.assert_array_equal(r.keys, np.sort(keys))
+    # 5, 3, 7 -> bucket 0; 50 -> floor(4*50/100) = 2; 100, 1000, 2^32-1 lie
+    # above the bound -> bucket 3
+    assert r.counts.tolist() == [3, 0, 1, 3]

@@ -63,3 +63,27 @@ def test_segmented_keys_layout():
     keys, off = w.segmented_keys(num_segments=20, lo=16, base=64)
     assert off.dtype == np.uint64 and off[0] == 0 and int(off[-1]) == keys.size
     assert np.all(np.diff(off.astype(np.int64)) >= 16)
+
+
+def test_paper_cases_shapes_and_checksums():
+    """The six input cases of section 4: range, order, repeated value, and
+    the recorded checksums of their first 2^16-key instances."""
+    gold = json.load(open(os.path.join(HERE, "golden", "input_checksums.json")))["paper_cases"]
+    n = 1 << 16
+    for c in range(1, 7):
+        k, M = w.paper_case(c, n)
+        assert k.dtype == np.uint32 and k.shape == (n,)
+        assert int(k.max()) <= M
+        assert hex(w.checksum(k)) == gold[str(c)]
+    assert w.PAPER_CASE_M == {1: 10**6, 2: 10**6, 3: 10**6, 4: 10**4, 5: 10**8, 6: 10**6}
+    k2, _ = w.paper_case(2, n)
+    assert np.all(np.diff(k2.astype(np.int64)) >= 0)
+    k3, _ = w.paper_case(3, n)
+    # at least 90% of adjacent pairs stay in order (n/20 replaced positions)
+    assert (np.diff(k3.astype(np.int64)) >= 0).mean() > 0.9
+    k6, M = w.paper_case(6, n)
+    assert int((k6 == M // 2).sum()) == n // 3
+    others = k6[k6 != M // 2]
+    assert np.unique(others).size == others.size   # distinct when they fit
+    big, _ = w.paper_case(6, 3 * 10**6)            # 2*10^6 others cannot be distinct in [0, 10^6]
+    assert int((big == 500_000).sum()) == 10**6

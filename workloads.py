@@ -147,6 +147,78 @@ def config2_keys(dist: int | str, n: int, seed: int | None = None) -> np.ndarray
     raise ValueError(f"unknown distribution {dist}")
 
 
+# ---- the paper's six input cases (section 4): n keys in [0, M]
+
+PAPER_CASE_M = {1: 10**6, 2: 10**6, 3: 10**6, 4: 10**4, 5: 10**8, 6: 10**6}
+
+
+def _uniform_upto(seed: int, stream: int, n: int, M: int) -> np.ndarray:
+    """n keys uniform in [0, M]: floor(u * (M + 1)) for a 32-bit u, exact."""
+    out = np.empty(n, dtype=np.uint32)
+    for lo in range(0, n, _CHUNK):
+        hi = min(n, lo + _CHUNK)
+        u = u64_stream(seed, stream, hi - lo, lo) >> np.uint64(32)
+        out[lo:hi] = ((u * np.uint64(M + 1)) >> np.uint64(32)).astype(np.uint32)
+    return out
+
+
+def _distinct_below(seed: int, count: int, U: int) -> np.ndarray:
+    """count distinct values in [0, U) (count <= U): the first count values of
+    x -> (a*x + c) mod 2^b restricted to [0, U) by cycle walking, a odd."""
+    b = max(1, (U - 1).bit_length())
+    mask = np.uint64((1 << b) - 1)
+    a = np.uint64((stream_base(seed, 7) | 1) & int(mask))
+    c = np.uint64(stream_base(seed, 8) & int(mask))
+    x = np.arange(count, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        y = (x * a + c) & mask
+        bad = y >= np.uint64(U)
+        while bad.any():
+            y[bad] = (y[bad] * a + c) & mask
+            bad = y >= np.uint64(U)
+    return y
+
+
+def paper_case(case: int, n: int, seed: int | None = None):
+    """(keys, M) for input case 1..6 of section 4 at size n, uint32 keys:
+      1  uniform in [0, M], M = 10^6
+      2  case 1 sorted
+      3  case 1 sorted, then n/20 positions (stream 1) take new uniform values
+         (stream 2): 95% of the keys stay in sorted order
+      4  uniform, M = 10^4
+      5  uniform, M = 10^8
+      6  n/3 keys equal to k = M/2, the rest distinct values in [0, M] other
+         than k when they fit (n - n/3 <= M), else uniform in [0, M] without
+         k; positions shuffled (stream 3), M = 10^6
+    seed defaults to 10 + case."""
+    if seed is None:
+        seed = 10 + case
+    M = PAPER_CASE_M[case]
+    if case in (1, 4, 5):
+        return _uniform_upto(seed, 0, n, M), M
+    if case in (2, 3):
+        a = np.sort(_uniform_upto(seed, 0, n, M), kind="stable")
+        if case == 3 and n >= 20:
+            m = n // 20
+            r = u64_stream(seed, 1, m) >> np.uint64(32)
+            pos = ((r * np.uint64(n)) >> np.uint64(32)).astype(np.int64)
+            a[pos] = _uniform_upto(seed, 2, m, M)
+        return a, M
+    if case == 6:
+        k = M // 2
+        same = n // 3
+        rest = n - same
+        if rest <= M:
+            v = _distinct_below(seed, rest, M)             # [0, M)
+        else:
+            v = _uniform_upto(seed, 4, rest, M - 1).astype(np.uint64)
+        v = v + (v >= np.uint64(k))                        # skip k: [0, M] without k
+        keys = np.concatenate([np.full(same, k, dtype=np.uint64), v]).astype(np.uint32)
+        order = np.argsort(u64_stream(seed, 3, n), kind="stable")
+        return np.ascontiguousarray(keys[order]), M
+    raise ValueError(f"unknown case {case}")
+
+
 def config3_pairs(variant: str, n: int):
     """uint64 keys (variant 'full': uniform [0, 2^64), seed 0; 'b40': uniform
     [0, 2^40), seed 1) with the uint32 payload 0..n-1."""
