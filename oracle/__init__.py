@@ -13,6 +13,9 @@ arrays.  Every function follows a passage of the paper:
                     for small buckets and a stable merge sort for large ones.
 * ``segmented``  -- either sort applied to every segment of a packed array.
 * ``bucket_index`` -- the exact bucket map floor((k-min)*B/(max-min+1)).
+* ``sort_ordered`` -- the definition of sorting (section 2) for signed and
+                    IEEE 754 keys: a stable merge sort under signed order or
+                    IEEE 754-2019 totalOrder.
 
 All results are pinned by ``tests/test_oracle_pins.py`` against library sorts,
 brute force and the invariants the paper states (sortedness, permutation,
@@ -62,6 +65,8 @@ def _load(path: str | None = None):
                                      ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_uint64, ctypes.c_uint64]
     lib.oracle_segmented.restype = ctypes.c_int
+    lib.oracle_sort_ordered.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_uint64]
+    lib.oracle_sort_ordered.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -184,4 +189,26 @@ def segmented(keys, offsets, vals=None, algo: str = "radix", r: int = 8,
     _check(lib.oracle_segmented(_ptr(keys), _ptr(out), w, _ptr(vals), _ptr(vout), n,
                                 _ptr(offsets), s, 0 if algo == "radix" else 1, r,
                                 num_buckets, cutoff))
+    return out, vout
+
+
+# numpy dtype -> key order understood by oracle_sort_ordered
+_ORDERS = {np.dtype(np.uint32): 0, np.dtype(np.uint64): 0, np.dtype(np.int32): 1, np.dtype(np.int64): 1,
+           np.dtype(np.float32): 2, np.dtype(np.float64): 2}
+
+
+def sort_ordered(keys, vals=None):
+    """Stable nondecreasing sort of unsigned, signed (by value) or IEEE 754
+    keys (totalOrder: -NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN, NaNs
+    by payload).  Returns (keys, vals) with the input's bit patterns."""
+    lib = _load()
+    keys = np.ascontiguousarray(keys)
+    if keys.dtype not in _ORDERS:
+        raise TypeError(f"unsupported key dtype {keys.dtype}")
+    n = keys.shape[0]
+    vals = _vals(vals, n)
+    out = np.empty_like(keys)
+    vout = None if vals is None else np.empty_like(vals)
+    _check(lib.oracle_sort_ordered(_ptr(keys), _ptr(out), keys.dtype.itemsize, _ORDERS[keys.dtype],
+                                   _ptr(vals), _ptr(vout), n))
     return out, vout

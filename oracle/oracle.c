@@ -18,6 +18,9 @@
  *     COUNTING-SORT (Algorithm 3): zero the counts, count every digit value,
  *     turn counts into inclusive prefix sums, then place elements from the
  *     last one to the first, decrementing the count of the element's digit.
+ *   - Keys that are not unsigned (signed integers, IEEE 754 floats): the same
+ *     definition of sorting under the order those bit patterns denote (signed
+ *     value; IEEE 754-2019 totalOrder), by a plain stable merge sort.
  *   - BUCKET-SORT (Algorithm 2): drop every element, in input order, into the
  *     bucket its value selects; sort every bucket with INSERTION-SORT
  *     (Algorithm 1, whose strict '>' keeps it stable); concatenate buckets.
@@ -389,5 +392,90 @@ int oracle_segmented(const void *keys_in, void *keys_out, int key_bytes,
                                cutoff, 0, NULL, NULL, NULL, NULL, NULL);
         if (rc != ORACLE_OK) return rc;
     }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------ signed and floating-point keys */
+
+/*
+ * The paper's keys are integers (section 2) and its algorithms compare them
+ * by value.  For keys that are not unsigned, "nondecreasing" needs an order
+ * on the bit patterns:
+ *   order 0: unsigned integers;
+ *   order 1: two's-complement signed integers, by value;
+ *   order 2: IEEE 754 binary32/binary64 in the totalOrder predicate of
+ *            IEEE 754-2019 section 5.10: a key with the sign bit set comes
+ *            before one without; between two keys without it the smaller
+ *            magnitude (the remaining bits read as an unsigned integer)
+ *            comes first; between two with it the larger magnitude comes
+ *            first.  This places -NaN < -inf < negatives < -0 < +0 <
+ *            positives < +inf < +NaN, NaNs ordered by their payload bits.
+ * key_before(a, b) is the strict "a comes before b" of that order.
+ */
+static int key_before(uint64_t a, uint64_t b, int key_bytes, int order)
+{
+    const unsigned top = 8u * (unsigned)key_bytes - 1u;
+    if (order == 0) return a < b;
+    if (order == 1) {
+        int64_t sa, sb;
+        if (key_bytes == 4) { sa = (int32_t)(uint32_t)a; sb = (int32_t)(uint32_t)b; }
+        else { sa = (int64_t)a; sb = (int64_t)b; }
+        return sa < sb;
+    }
+    const uint64_t neg_a = (a >> top) & 1u, neg_b = (b >> top) & 1u;
+    const uint64_t mag_mask = (top == 63u) ? ~(uint64_t)0 >> 1 : (((uint64_t)1 << top) - 1u);
+    const uint64_t ma = a & mag_mask, mb = b & mag_mask;
+    if (neg_a != neg_b) return neg_a > neg_b;
+    if (neg_a) return ma > mb;
+    return ma < mb;
+}
+
+/*
+ * Stable sort of n keys in the order above (payload optional): a bottom-up
+ * merge sort that takes the right run's key only when it comes strictly
+ * before the left run's, so keys with equal bits keep their input order --
+ * the stable permutation of section 2's definition, unique for each input.
+ */
+int oracle_sort_ordered(const void *keys_in, void *keys_out, int key_bytes, int order,
+                        const uint32_t *vals_in, uint32_t *vals_out, uint64_t n)
+{
+    if (key_bytes != 4 && key_bytes != 8) return ORACLE_EINVAL;
+    if (order < 0 || order > 2) return ORACLE_EINVAL;
+    if ((vals_in == NULL) != (vals_out == NULL)) return ORACLE_EINVAL;
+    if (n == 0) return ORACLE_OK;
+    if (!keys_in || !keys_out) return ORACLE_EINVAL;
+    uint64_t *a = widen(keys_in, n, key_bytes);
+    uint64_t *t = (uint64_t *)malloc(n * sizeof(uint64_t));
+    uint32_t *v = NULL, *tv = NULL;
+    if (vals_in) {
+        v = (uint32_t *)malloc(n * sizeof(uint32_t));
+        tv = (uint32_t *)malloc(n * sizeof(uint32_t));
+        if (v) memcpy(v, vals_in, n * sizeof(uint32_t));
+    }
+    if (!a || !t || (vals_in && (!v || !tv))) {
+        free(a); free(t); free(v); free(tv);
+        return ORACLE_ENOMEM;
+    }
+    uint64_t *src = a, *dst = t;
+    uint32_t *vs = v, *vd = tv;
+    for (uint64_t width = 1; width < n; width *= 2) {
+        for (uint64_t lo = 0; lo < n; lo += 2 * width) {
+            uint64_t mid = lo + width < n ? lo + width : n;
+            uint64_t hi = lo + 2 * width < n ? lo + 2 * width : n;
+            uint64_t i = lo, j = mid, o = lo;
+            while (i < mid || j < hi) {
+                int right = i == mid || (j < hi && key_before(src[j], src[i], key_bytes, order));
+                uint64_t from = right ? j++ : i++;
+                dst[o] = src[from];
+                if (v) vd[o] = vs[from];
+                o++;
+            }
+        }
+        uint64_t *x = src; src = dst; dst = x;
+        uint32_t *y = vs; vs = vd; vd = y;
+    }
+    narrow(src, keys_out, n, key_bytes);
+    if (vals_out) memcpy(vals_out, vs, n * sizeof(uint32_t));
+    free(a); free(t); free(v); free(tv);
     return ORACLE_OK;
 }

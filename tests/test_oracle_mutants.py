@@ -39,6 +39,17 @@ MUTANTS = [
      "if (A[i] < mn) mn = A[i];", "if (0) mn = A[i];"),
     ("payload not moved in the digit sort",
      "if (VA) VB[C[dg]] = VA[j];", "if (VA) VB[C[dg]] = VA[C[dg]];"),
+    ("signed keys compared as unsigned",
+     "return sa < sb;", "return a < b;"),
+    ("float sign orders positives first",
+     "if (neg_a != neg_b) return neg_a > neg_b;", "if (neg_a != neg_b) return neg_a < neg_b;"),
+    ("negative floats by ascending magnitude",
+     "if (neg_a) return ma > mb;", "if (neg_a) return ma < mb;"),
+    ("sign bit of 32-bit keys taken from bit 63",
+     "const unsigned top = 8u * (unsigned)key_bytes - 1u;", "const unsigned top = 63u;"),
+    ("ordered merge takes right run on ties",
+     "(j < hi && key_before(src[j], src[i], key_bytes, order))",
+     "(j < hi && !key_before(src[i], src[j], key_bytes, order))"),
 ]
 
 CHECK = textwrap.dedent(r'''
@@ -92,6 +103,28 @@ CHECK = textwrap.dedent(r'''
     res = oracle.bucket(kk, num_buckets=3000, key_bound=10**6, want_intermediates=True)
     want = np.bincount([(3000 * int(x)) // (10**6 + 1) for x in kk], minlength=3000)
     ok &= np.array_equal(res.counts.astype(np.int64), want)
+    # signed keys against the library sort; IEEE keys on a totalOrder ladder
+    for dt in (np.int32, np.int64):
+        info = np.iinfo(dt)
+        k = rng.integers(info.min, info.max, 3000, dtype=dt, endpoint=True)
+        k[::7] = k[3]
+        v = np.arange(3000, dtype=np.uint32)
+        rk, rv = oracle.sort_ordered(k, v)
+        ek, ev = ref(k, v)
+        ok &= np.array_equal(rk, ek) and np.array_equal(rv, ev)
+    for fdt, ut, lad in ((np.float32, np.uint32, [0xFFC00000, 0xFF800000, 0xBF800000, 0x80000000,
+                                                  0x00000000, 0x3F800000, 0x7F800000, 0x7FC00000]),
+                         (np.float64, np.uint64, [0xFFF8000000000000, 0xFFF0000000000000,
+                                                  0xBFF0000000000000, 0x8000000000000000, 0,
+                                                  0x3FF0000000000000, 0x7FF0000000000000,
+                                                  0x7FF8000000000000])):
+        lad = np.array(lad, dtype=ut)
+        idx = np.repeat(np.arange(lad.size), 3)
+        rng.shuffle(idx)
+        v = np.arange(idx.size, dtype=np.uint32)
+        rk, rv = oracle.sort_ordered(lad[idx].view(fdt), v)
+        o = np.argsort(idx, kind="stable")
+        ok &= np.array_equal(rk.view(ut), lad[idx[o]]) and np.array_equal(rv, v[o])
     sys.exit(0 if ok else 3)
 ''')
 

@@ -288,3 +288,118 @@ def test_bucket_keys_above_declared_bound_join_last_bucket():
     # 5, 3, 7 -> bucket 0; 50 -> floor(4*50/100) = 2; 100, 1000, 2^32-1 lie
     # above the bound -> bucket 3
     assert r.counts.tolist() == [3, 0, 1, 3]
+
+
+# ------------------------------------------- signed and floating-point keys
+
+# IEEE 754 binary32 / binary64 bit patterns in ascending totalOrder
+# (IEEE 754-2019 section 5.10), written from the formats' fields
+# (sign | exponent | fraction): -NaN with the largest payload, -qNaN, -sNaN,
+# -inf, -max, -1, -min normal, -max subnormal, -min subnormal, -0, and the
+# mirror images ascending.
+F32_LADDER = [0xFFFFFFFF, 0xFFC00000, 0xFF800001, 0xFF800000, 0xFF7FFFFF, 0xBF800000, 0x80800000,
+              0x807FFFFF, 0x80000001, 0x80000000,
+              0x00000000, 0x00000001, 0x007FFFFF, 0x00800000, 0x3F800000, 0x7F7FFFFF, 0x7F800000,
+              0x7F800001, 0x7FC00000, 0x7FFFFFFF]
+F64_LADDER = [0xFFFFFFFFFFFFFFFF, 0xFFF8000000000000, 0xFFF0000000000001, 0xFFF0000000000000,
+              0xFFEFFFFFFFFFFFFF, 0xBFF0000000000000, 0x8010000000000000, 0x800FFFFFFFFFFFFF,
+              0x8000000000000001, 0x8000000000000000,
+              0x0000000000000000, 0x0000000000000001, 0x000FFFFFFFFFFFFF, 0x0010000000000000,
+              0x3FF0000000000000, 0x7FEFFFFFFFFFFFFF, 0x7FF0000000000000, 0x7FF0000000000001,
+              0x7FF8000000000000, 0x7FFFFFFFFFFFFFFF]
+
+
+def _ladder(fdt):
+    bits = np.array(F32_LADDER if fdt == np.float32 else F64_LADDER,
+                    dtype=np.uint32 if fdt == np.float32 else np.uint64)
+    return bits.view(fdt)
+
+
+@pytest.mark.parametrize("fdt", [np.float32, np.float64])
+def test_float_ladder_is_what_it_claims(fdt):
+    """The hand-written ladder: NaNs at both ends, the finite values and the
+    infinities strictly ascending by value except -0 == +0, -0 carrying the
+    sign bit."""
+    v = _ladder(fdt)
+    nan = np.isnan(v)
+    assert nan[:3].all() and nan[-3:].all() and not nan[3:-3].any()
+    assert np.signbit(v[:10]).all() and not np.signbit(v[10:]).any()
+    mid = v[3:-3].astype(np.float64)
+    d = np.diff(mid)
+    assert (d[d != 0] > 0).all() and np.count_nonzero(d == 0) == 1
+    assert v[3] == -np.inf and v[-4] == np.inf
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+@pytest.mark.parametrize("n", [0, 1, 5, 4097])
+def test_signed_order_matches_library(dtype, n):
+    info = np.iinfo(dtype)
+    k = RNG.integers(info.min, info.max, n, dtype=dtype, endpoint=True)
+    if n > 8:
+        k[:6] = [info.min, info.max, -1, 0, 1, info.min]
+        k[::9] = k[4]
+    v = np.arange(n, dtype=np.uint32)
+    got_k, got_v = oracle.sort_ordered(k, v)
+    ek, ev = stable_ref(k, v)
+    np.testing.assert_array_equal(got_k, ek)
+    np.testing.assert_array_equal(got_v, ev)
+
+
+@pytest.mark.parametrize("fdt", [np.float32, np.float64])
+def test_float_finite_order_matches_library(fdt):
+    """Finite keys without -0: totalOrder is the numeric order, and the stable
+    library sort fixes the payload order of equal keys."""
+    n = 5000
+    k = (RNG.standard_normal(n) * np.exp(RNG.uniform(-30, 30, n))).astype(fdt)
+    k[::11] = k[3]
+    k[::13] = 0.0
+    k[k == 0] = 0.0          # no -0: numeric order cannot tell it from +0
+    v = np.arange(n, dtype=np.uint32)
+    got_k, got_v = oracle.sort_ordered(k, v)
+    ek, ev = stable_ref(k, v)
+    np.testing.assert_array_equal(got_k.view(np.uint8), ek.view(np.uint8))
+    np.testing.assert_array_equal(got_v, ev)
+
+
+@pytest.mark.parametrize("fdt", [np.float32, np.float64])
+def test_float_specials_follow_total_order(fdt):
+    """Every ladder entry, repeated and shuffled: the output lists the ladder
+    in order (by bit pattern) and keeps the input order of repeats."""
+    lad = _ladder(fdt)
+    ut = np.uint32 if fdt == np.float32 else np.uint64
+    idx = np.repeat(np.arange(lad.size), 3)
+    RNG.shuffle(idx)
+    k = lad[idx]
+    v = np.arange(idx.size, dtype=np.uint32)
+    got_k, got_v = oracle.sort_ordered(k, v)
+    order = np.argsort(idx, kind="stable")
+    np.testing.assert_array_equal(got_k.view(ut), lad[idx[order]].view(ut))
+    np.testing.assert_array_equal(got_v, v[order])
+
+
+@pytest.mark.parametrize("fdt", [np.float32, np.float64])
+def test_float_order_brute_force_on_ladder(fdt):
+    """Every sequence of length <= 4 over six ladder entries (-NaN, -inf, -0,
+    +0, +inf, +NaN and neighbours): the result is the stable sort by ladder
+    position."""
+    lad = _ladder(fdt)
+    pick = [1, 3, 9, 10, 16, 18]
+    ut = np.uint32 if fdt == np.float32 else np.uint64
+    for m in range(5):
+        for seq in itertools.product(range(len(pick)), repeat=m):
+            pos = np.array([pick[s] for s in seq], dtype=np.int64)
+            k = lad[pos]
+            got_k, got_v = oracle.sort_ordered(k, np.arange(m, dtype=np.uint32))
+            order = sorted(range(m), key=lambda i: pos[i])
+            assert got_k.view(ut).tolist() == lad[pos[order]].view(ut).tolist()
+            assert got_v.tolist() == order
+
+
+def test_unsigned_order_equals_radix():
+    k = rand_keys(3000, np.uint64)
+    k[::5] = k[2]
+    v = np.arange(3000, dtype=np.uint32)
+    got_k, got_v = oracle.sort_ordered(k, v)
+    ek, ev = stable_ref(k, v)
+    np.testing.assert_array_equal(got_k, ek)
+    np.testing.assert_array_equal(got_v, ev)
