@@ -56,9 +56,26 @@ typedef enum intsort_status {
     INTSORT_ERR_NOT_READY = 8         /* serving: the ticket has not completed yet */
 } intsort_status;
 
+/*
+ * Key types.  The paper sorts non-negative integers (section 2); unsigned
+ * keys are that case.  Signed and floating-point keys are sorted by radix
+ * sort with 8-bit digits only (any other algorithm, digit width or entry
+ * point returns INTSORT_ERR_UNSUPPORTED): each digit is taken from an
+ * order-preserving image of the key's bits, and the original bits are what
+ * move, so the output holds the input's bit patterns.
+ *   I32/I64  two's complement, ascending by value.
+ *   F32/F64  IEEE 754 binary32/binary64 in the totalOrder of IEEE 754-2019
+ *            section 5.10: -NaN < -inf < finite negatives < -0 < +0 <
+ *            finite positives < +inf < +NaN, NaNs ordered by their payload
+ *            bits; keys with identical bits keep their input order.
+ */
 typedef enum intsort_key_type {
     INTSORT_U32 = 0,
-    INTSORT_U64 = 1
+    INTSORT_U64 = 1,
+    INTSORT_I32 = 2,
+    INTSORT_I64 = 3,
+    INTSORT_F32 = 4,
+    INTSORT_F64 = 5
 } intsort_key_type;
 
 typedef enum intsort_algo {

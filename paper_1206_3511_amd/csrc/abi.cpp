@@ -22,9 +22,23 @@ namespace {
 
 using namespace intsort;
 
-int key_bytes_of(intsort_key_type kt) { return kt == INTSORT_U64 ? 8 : 4; }
+int key_bytes_of(intsort_key_type kt)
+{
+    return kt == INTSORT_U64 || kt == INTSORT_I64 || kt == INTSORT_F64 ? 8 : 4;
+}
 
-bool valid_kt(intsort_key_type kt) { return kt == INTSORT_U32 || kt == INTSORT_U64; }
+bool valid_kt(intsort_key_type kt) { return kt >= INTSORT_U32 && kt <= INTSORT_F64; }
+
+bool unsigned_kt(intsort_key_type kt) { return kt == INTSORT_U32 || kt == INTSORT_U64; }
+
+// how a key's bits map to its rank: 0 as unsigned, 1 two's complement,
+// 2 IEEE 754 totalOrder
+int key_order(intsort_key_type kt)
+{
+    if (kt == INTSORT_I32 || kt == INTSORT_I64) return 1;
+    if (kt == INTSORT_F32 || kt == INTSORT_F64) return 2;
+    return 0;
+}
 
 intsort_status read_opts(const intsort_options *in, intsort_key_type kt, intsort_options *out)
 {
@@ -36,6 +50,8 @@ intsort_status read_opts(const intsort_options *in, intsort_key_type kt, intsort
     if (out->algo != INTSORT_RADIX_LSD && out->algo != INTSORT_BUCKET) return INTSORT_ERR_INVALID_ARGUMENT;
     if (out->digit_bits == 0) out->digit_bits = 8;
     if (out->digit_bits != 4 && out->digit_bits != 8 && out->digit_bits != 11) return INTSORT_ERR_UNSUPPORTED;
+    // signed and floating-point keys: radix sort with 8-bit digits only
+    if (!unsigned_kt(kt) && (out->algo != INTSORT_RADIX_LSD || out->digit_bits != 8)) return INTSORT_ERR_UNSUPPORTED;
     if (out->num_buckets == 0) out->num_buckets = kt == INTSORT_U64 ? 65536u : 1024u;
     if (out->num_buckets > MAX_BUCKETS) return INTSORT_ERR_UNSUPPORTED;
     if (out->flags & ~INTSORT_FLAG_NO_PASS_SKIP) return INTSORT_ERR_INVALID_ARGUMENT;
@@ -128,6 +144,7 @@ intsort_status sort_common(intsort_ctx *ctx, intsort_key_type kt, const void *ke
         c.key_bytes = kb;
         c.pairs = pairs;
         c.bits = (int)o.digit_bits;
+        c.order = key_order(kt);
         c.L = radix_layout(kb, pairs, n, c.bits);
         c.max_passes = c.L.g.passes;
         c.skip_constant_digits = !(o.flags & INTSORT_FLAG_NO_PASS_SKIP);
@@ -283,7 +300,7 @@ intsort_status intsort_workspace_size(const intsort_ctx *ctx, intsort_key_type k
         if (num_segments == 0) {
             *bytes = plain;
         } else {
-            if (num_segments > MAX_SEGMENTS) return INTSORT_ERR_UNSUPPORTED;
+            if (num_segments > MAX_SEGMENTS || !unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
             *bytes = segmented_layout(kb, has_values != 0, n, num_segments, o).total;
         }
         return INTSORT_OK;
@@ -324,6 +341,7 @@ static intsort_status segmented_common(intsort_ctx *ctx, intsort_key_type kt, co
                                        size_t ws_bytes, void *stream)
 {
     if (!ctx || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (!unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
     intsort_options o;
     intsort_status st = read_opts(opts_in, kt, &o);
     if (st != INTSORT_OK) return st;
@@ -390,6 +408,7 @@ intsort_status intsort_batched_sort_keys(intsort_ctx *ctx, intsort_key_type kt, 
 {
     try {
         if (!ctx || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (!unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
         intsort_options o;
         intsort_status st = read_opts(opts, kt, &o);
         if (st != INTSORT_OK) return st;
@@ -423,6 +442,7 @@ intsort_status intsort_digit_histogram(intsort_ctx *ctx, intsort_key_type kt, co
 {
     try {
         if (!ctx || !valid_kt(kt) || !counts) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (!unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
         if (digit_bits != 4 && digit_bits != 8 && digit_bits != 11) return INTSORT_ERR_UNSUPPORTED;
         if (n > 0 && !keys) return INTSORT_ERR_INVALID_ARGUMENT;
         if (n > 0 && !aligned16(keys)) return INTSORT_ERR_MISALIGNED;
@@ -450,6 +470,7 @@ intsort_status intsort_minmax(intsort_ctx *ctx, intsort_key_type kt, const void 
 {
     try {
         if (!ctx || !valid_kt(kt) || !minmax || n == 0 || !keys) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (!unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
         if (!aligned16(keys)) return INTSORT_ERR_MISALIGNED;
         intsort_status st = set_device(ctx);
         if (st != INTSORT_OK) return st;
@@ -465,6 +486,7 @@ intsort_status intsort_bucket_histogram(intsort_ctx *ctx, intsort_key_type kt, c
 {
     try {
         if (!ctx || !valid_kt(kt) || !minmax || !counts || num_buckets == 0) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (!unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
         if (n > 0 && !keys) return INTSORT_ERR_INVALID_ARGUMENT;
         if (num_buckets > MAX_BUCKETS || n >= (1ull << 32)) return INTSORT_ERR_UNSUPPORTED;
         intsort_status st = set_device(ctx);

@@ -4,9 +4,9 @@
 // for keys in [0, M].  With the value range measured instead of assumed and
 // B buckets, the bucket of key k is
 //     b(k) = floor((k - min) * B / R),   R = max - min + 1,
-// which is nondecreasing in k, maps min to 0 and stays below B.  The product
-// (k - min) * B needs 52 bits for 32-bit keys and up to 84 bits for 64-bit
-// keys, and R can be 2^64.  A double-precision quotient gives an estimate that
+// which is nondecreasing in k, maps min to 0 and stays below B.  With B up to
+// 2^30 the product (k - min) * B needs up to 62 bits for 32-bit keys and up
+// to 94 bits for 64-bit keys, and R can be 2^64.  A double-precision quotient gives an estimate that
 // is at most one away from b(k); exact integer arithmetic then corrects it, so
 // the result is exact for every key.
 #pragma once
@@ -39,10 +39,10 @@ __device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, u
     return m;
 }
 
-// b(k) for 32-bit keys.  num = (k - min) * B is below 2^48; with
+// b(k) for 32-bit keys.  num = (k - min) * B is below 2^62; with
 // inv = floor((2^64 - 1) / R) the estimate floor(num * inv / 2^64) is either
-// the exact quotient or one less (num * inv / 2^64 lies within num / 2^64 < 1
-// of num / R), so one remainder check makes it exact.  The result is clamped
+// the exact quotient or one less (num * inv / 2^64 lies below num / R and
+// within 2 num / 2^64 < 1/2 of it), so one remainder check makes it exact.  The result is clamped
 // so that a key outside [min, max] cannot index past B.
 __device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint32_t k)
 {

@@ -118,8 +118,8 @@ __device__ __forceinline__ void blocked_via_lds(const T *src, uint32_t valid, T 
 }
 
 // digit counts of every chunk
-template <typename K, int BITS>
-__global__ __launch_bounds__(512) void k_chunk_count(PassArgs<K> a, ChunkArgs ca, RadixDigit dg)
+template <typename K, int BITS, class DG>
+__global__ __launch_bounds__(512) void k_chunk_count(PassArgs<K> a, ChunkArgs ca, DG dg)
 {
     using C = ChunkCfg<K, BITS>;
     constexpr int RADIX = C::RADIX, TILE = C::TILE;
@@ -184,9 +184,9 @@ __global__ __launch_bounds__(256) void k_chunk_scan(ChunkArgs ca, uint32_t radix
     }
 }
 
-template <typename K, int BITS, bool PAIRS>
+template <typename K, int BITS, bool PAIRS, class DG>
 __global__ __launch_bounds__((ChunkCfg<K, BITS>::NT), (PAIRS ? 2 : 4)) void k_chunk_sort(PassArgs<K> a, ChunkArgs ca,
-                                                                                     RadixDigit dg)
+                                                                                     DG dg)
 {
     using C = ChunkCfg<K, BITS>;
     constexpr int RADIX = C::RADIX, NT = C::NT, IPT = C::IPT, TILE = C::TILE;
@@ -245,15 +245,15 @@ __global__ __launch_bounds__((ChunkCfg<K, BITS>::NT), (PAIRS ? 2 : 4)) void k_ch
         __syncthreads();
 
         // ---- the tile in blocked order: thread t holds positions t*IPT ..;
-        // padding past the end is all ones, whose digit is the largest, so
-        // it sorts after every key
+        // padding past the end is the largest key, whose digit is the
+        // largest, so it sorts after every key
         K k[IPT];
         uint32_t v[IPT];
         if (valid == (uint32_t)TILE) {
             blocked_from_global<K, IPT>(src + start + (uint64_t)tid * IPT, k);
             if constexpr (PAIRS) blocked_from_global<uint32_t, IPT>(vsrc + start + (uint64_t)tid * IPT, v);
         } else {
-            blocked_via_lds<K, IPT, NT>(src + start, valid, ~K(0), s_stage, k);
+            blocked_via_lds<K, IPT, NT>(src + start, valid, dg.template pad<K>(), s_stage, k);
             if constexpr (PAIRS) blocked_via_lds<uint32_t, IPT, NT>(vsrc + start, valid, 0u, s_stage, v);
             for (uint32_t d = tid; d < (uint32_t)RADIX; d += NT) s_hist[d] = 0;
             __syncthreads();

@@ -96,6 +96,7 @@ struct RadixCall {
     int key_bytes;
     bool pairs;
     int bits;
+    int order;        // 0 unsigned, 1 signed, 2 IEEE 754 totalOrder
     bool skip_constant_digits;
     int max_passes;   // passes to run at most (<= geometry passes)
     char *ws;         // workspace base

@@ -57,22 +57,56 @@ __device__ __forceinline__ uint32_t digit_at(K k, uint32_t shift, uint32_t mask)
     return (uint32_t)(k >> shift) & mask;
 }
 
-// digit p of radix sort: (k >> p*r) & (2^r - 1)
-struct RadixDigit {
-    // an all-ones key has the largest digit: padding past a tile's end needs
-    // no separate check
-    static constexpr bool ONES_IS_MAX = true;
-    uint32_t shift, mask;
-    __device__ RadixDigit prepare() const { return *this; }
+// Order of the keys' bit patterns: 0 unsigned; 1 two's-complement signed;
+// 2 IEEE 754 totalOrder (binary32/binary64: -NaN < -inf < ... < -0 < +0 <
+// ... < +inf < +NaN).  ordered(k) maps a key to an unsigned value with the
+// same order: signed keys flip the sign bit, floats flip the sign bit of a
+// positive value and every bit of a negative one.
+template <int ORDER>
+struct KeyOrder {
     template <typename K>
-    __device__ __forceinline__ uint32_t operator()(K k) const { return digit_at<K>(k, shift, mask); }
+    __device__ __forceinline__ static K ordered(K k)
+    {
+        constexpr int TOP = 8 * (int)sizeof(K) - 1;
+        constexpr K SIGN = K(1) << TOP;
+        if (ORDER == 1) return k ^ SIGN;
+        if (ORDER == 2) {
+            using S = std::make_signed_t<K>;
+            return k ^ ((K)((S)k >> TOP) | SIGN);
+        }
+        return k;
+    }
+    // the key whose ordered value is all ones: it sorts after every key
+    template <typename K>
+    __device__ __forceinline__ static K largest()
+    {
+        return ORDER == 0 ? ~K(0) : (K)(~K(0) >> 1);
+    }
+};
+
+// digit p of radix sort: (ordered(k) >> p*r) & (2^r - 1)
+template <int ORDER>
+struct OrderedDigit {
+    // padding past a tile's end is the largest key, whose digit is the
+    // largest: it needs no separate check
+    static constexpr bool PAD_IS_MAX = true;
+    uint32_t shift, mask;
+    __device__ OrderedDigit prepare() const { return *this; }
+    template <typename K>
+    __device__ __forceinline__ uint32_t operator()(K k) const
+    {
+        return digit_at<K>(KeyOrder<ORDER>::ordered(k), shift, mask);
+    }
     // bits lo .. lo+w-1 of the digit
     template <typename K>
     __device__ __forceinline__ uint32_t sub(K k, uint32_t lo, uint32_t w) const
     {
-        return (uint32_t)(k >> (shift + lo)) & ((1u << w) - 1u);
+        return (uint32_t)(KeyOrder<ORDER>::ordered(k) >> (shift + lo)) & ((1u << w) - 1u);
     }
+    template <typename K>
+    __device__ __forceinline__ K pad() const { return KeyOrder<ORDER>::template largest<K>(); }
 };
+using RadixDigit = OrderedDigit<0>;
 
 // an 8-bit field of the bucket index b(k) of bucket sort; min and max are
 // read from device memory when the kernel starts
@@ -80,11 +114,14 @@ struct BucketDigitArgs {
     const uint64_t *minmax;
     uint32_t buckets, shift, mask;
     struct Fn {
-        static constexpr bool ONES_IS_MAX = false;
+        static constexpr bool PAD_IS_MAX = false;
         BucketMap m;
         uint32_t shift, mask;
         template <typename K>
         __device__ __forceinline__ uint32_t operator()(K k) const { return (bucket_of(m, k) >> shift) & mask; }
+        // padding past a tile's end: any key; its digit is replaced by the largest
+        template <typename K>
+        __device__ __forceinline__ K pad() const { return ~K(0); }
     };
     __device__ Fn prepare() const { return Fn{make_bucket_map(minmax[0], minmax[1], buckets), shift, mask}; }
 };
@@ -497,14 +534,14 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
             const bool in = lofs + j * WAVE < valid;
-            k[j] = in ? src[wofs + j * WAVE] : ~K(0);
+            k[j] = in ? src[wofs + j * WAVE] : dg.template pad<K>();
             if (PAIRS) v[j] = in ? vsrc[wofs + j * WAVE] : 0u;
         }
     }
     // keys past the end of the tile take the largest digit and so rank last
     using DG = std::remove_cv_t<decltype(dg)>;
     auto digit_of = [&](int j) -> uint32_t {
-        if (DG::ONES_IS_MAX) return dg(k[j]);
+        if (DG::PAD_IS_MAX) return dg(k[j]);
         return (valid == (uint32_t)TILE || lofs + j * WAVE < valid) ? dg(k[j]) : MASK;
     };
 

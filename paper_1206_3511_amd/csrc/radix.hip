@@ -77,7 +77,7 @@ struct HistArgs {
     uint32_t copies;       // histogram copies the workgroups spread their adds over
 };
 
-template <typename K, int BITS>
+template <typename K, int BITS, int ORDER>
 __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__restrict__ keys, HistArgs a)
 {
     constexpr int RADIX = 1 << BITS;
@@ -116,14 +116,15 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
                 for (int e = 0; e < KPV; e++) {
 #pragma unroll
                     for (int p = 0; p < PASSES; p++)
-                        lds_count(s_h + p * RADIX, digit_at<K>(x[u].v[e], (uint32_t)(p * BITS), MASK));
+                        lds_count(s_h + p * RADIX,
+                                  digit_at<K>(KeyOrder<ORDER>::ordered(x[u].v[e]), (uint32_t)(p * BITS), MASK));
                 }
             }
         }
     }
     if (blockIdx.x == 0) {
         for (uint32_t i = nvec * KPV + tid; i < n; i += HIST_THREADS) {
-            K k = keys[i];
+            const K k = KeyOrder<ORDER>::ordered(keys[i]);
 #pragma unroll
             for (int p = 0; p < PASSES; p++)
                 lds_count(s_h + p * RADIX, digit_at<K>(k, (uint32_t)(p * BITS), MASK));
@@ -303,7 +304,7 @@ static int current_cus()
     return device_cu_count(dev);
 }
 
-template <typename K, int BITS>
+template <typename K, int BITS, int ORDER = 0>
 static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool finalize, hipStream_t s)
 {
     using C = PassCfg<K, BITS>;
@@ -334,7 +335,7 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
     const uint64_t cap = (uint64_t)current_cus() * HIST_BLOCKS_PER_CU;
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL((k_digit_histogram<K, BITS>), dim3((uint32_t)blocks), dim3(HIST_THREADS), 0, s,
+    hipLaunchKernelGGL((k_digit_histogram<K, BITS, ORDER>), dim3((uint32_t)blocks), dim3(HIST_THREADS), 0, s,
                        static_cast<const K *>(c.keys_in), h);
     if (t) t->mark(INTSORT_KERNEL_DIGIT_HISTOGRAM, 0, s);
     if (finalize) {
@@ -344,14 +345,14 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
     return hipGetLastError();
 }
 
-template <typename K, int BITS, bool PAIRS>
+template <typename K, int BITS, bool PAIRS, int ORDER = 0>
 static hipError_t run_typed(const RadixCall &c, hipStream_t s)
 {
     using C = PassCfg<K, BITS>;
     const RadixLayout &L = c.L;
     char *ws = c.ws;
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
-    hipError_t e = launch_histogram<K, BITS>(c, hist, true, s);
+    hipError_t e = launch_histogram<K, BITS, ORDER>(c, hist, true, s);
     if (e != hipSuccess) return e;
 
     PassArgs<K> a{};
@@ -371,7 +372,8 @@ static hipError_t run_typed(const RadixCall &c, hipStream_t s)
     for (int p = 0; p < C::PASSES && p < c.max_passes; p++) {
         a.plan = plan + p * PLAN_WORDS;
         a.pass = (uint32_t)p;
-        const RadixDigit dg{(uint32_t)(p * BITS), (uint32_t)(C::RADIX - 1)};
+        using DG = OrderedDigit<ORDER>;
+        const DG dg{(uint32_t)(p * BITS), (uint32_t)(C::RADIX - 1)};
         if constexpr (chunked_pass<BITS>()) {
             using H = ChunkCfg<K, BITS>;
             ChunkArgs ca{};
@@ -386,12 +388,12 @@ static hipError_t run_typed(const RadixCall &c, hipStream_t s)
             ca.off = a.status1;
             ca.excl = excl + p * C::RADIX;
             ca.counters = a.counters;
-            hipLaunchKernelGGL((k_chunk_count<K, BITS>), dim3(ca.chunks), dim3(512), 0, s, a, ca, dg);
+            hipLaunchKernelGGL((k_chunk_count<K, BITS, DG>), dim3(ca.chunks), dim3(512), 0, s, a, ca, dg);
             hipLaunchKernelGGL(k_chunk_scan, dim3(C::RADIX), dim3(256), 0, s, ca, (uint32_t)C::RADIX);
-            hipLaunchKernelGGL((k_chunk_sort<K, BITS, PAIRS>), dim3(ca.chunks), dim3(H::NT), 0, s, a, ca, dg);
+            hipLaunchKernelGGL((k_chunk_sort<K, BITS, PAIRS, DG>), dim3(ca.chunks), dim3(H::NT), 0, s, a, ca, dg);
         } else {
             const PlainTiles tl{(uint32_t)c.n, (uint32_t)L.num_tiles, excl + p * C::RADIX};
-            hipLaunchKernelGGL((k_onesweep<K, BITS, PAIRS, RadixDigit, PlainTiles>), dim3((uint32_t)L.num_tiles),
+            hipLaunchKernelGGL((k_onesweep<K, BITS, PAIRS, DG, PlainTiles>), dim3((uint32_t)L.num_tiles),
                                dim3(C::NT), 0, s, a, dg, tl);
         }
         if (c.timer) c.timer->mark(INTSORT_KERNEL_PASS, (uint32_t)p, s);
@@ -409,6 +411,11 @@ static hipError_t run_typed(const RadixCall &c, hipStream_t s)
 template <typename K, bool PAIRS>
 static hipError_t run_bits(const RadixCall &c, hipStream_t s)
 {
+    // signed and floating-point keys: 8-bit digits
+    if (c.order != 0) {
+        if (c.bits != 8) return hipErrorNotSupported;
+        return c.order == 1 ? run_typed<K, 8, PAIRS, 1>(c, s) : run_typed<K, 8, PAIRS, 2>(c, s);
+    }
     switch (c.bits) {
     case 4: return run_typed<K, 4, PAIRS>(c, s);
     case 11: return run_typed<K, 11, PAIRS>(c, s);

@@ -26,7 +26,7 @@ ERR_HIP = 6
 ERR_INTERNAL = 7
 ERR_NOT_READY = 8
 
-U32, U64 = 0, 1
+U32, U64, I32, I64, F32, F64 = 0, 1, 2, 3, 4, 5
 RADIX, BUCKET = 0, 1
 FLAG_NO_PASS_SKIP = 0x1
 
@@ -196,12 +196,15 @@ def context(device: int) -> Context:
     return c
 
 
+_KEY_TYPES = {torch.uint32: U32, torch.uint64: U64, torch.int32: I32, torch.int64: I64,
+              torch.float32: F32, torch.float64: F64}
+
+
 def _key_type(t: torch.Tensor) -> int:
-    if t.dtype in (torch.uint32, torch.int32):
-        return U32
-    if t.dtype in (torch.uint64, torch.int64):
-        return U64
-    raise TypeError(f"keys must be a 32- or 64-bit integer tensor, got {t.dtype}")
+    kt = _KEY_TYPES.get(t.dtype)
+    if kt is None:
+        raise TypeError(f"keys must be a 32- or 64-bit integer or float tensor, got {t.dtype}")
+    return kt
 
 
 def _dev_tensor(t: torch.Tensor, what: str) -> torch.Tensor:
@@ -223,8 +226,10 @@ def _ptr(t):
 
 def sort(keys: torch.Tensor, algo: str = "radix", out: torch.Tensor | None = None, stream=None,
          **opt) -> torch.Tensor:
-    """Nondecreasing permutation of `keys` (uint32/int32 or uint64/int64 bit
-    patterns, sorted as unsigned)."""
+    """Nondecreasing permutation of `keys`.  Unsigned keys (uint32, uint64)
+    take every algorithm; signed (int32, int64) and floating-point keys
+    (float32, float64, in IEEE 754 totalOrder: -NaN < -inf < ... < -0 < +0
+    < ... < +inf < +NaN) take radix sort with 8-bit digits."""
     _dev_tensor(keys, "keys")
     kt = _key_type(keys)
     out = torch.empty_like(keys) if out is None else _dev_tensor(out, "out")

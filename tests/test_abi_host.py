@@ -112,3 +112,34 @@ def test_workspace_monotone(plan_ctx, kt, pairs, bits):
     # at least the scratch copy of keys (and values)
     w = 8 if kt == I.U64 else 4
     assert prev >= 10**8 * (w + (4 if pairs else 0))
+
+
+@pytest.mark.parametrize("kt,kb", [(I.I32, 4), (I.I64, 8), (I.F32, 4), (I.F64, 8)])
+def test_signed_and_float_keys_take_radix_with_8bit_digits(plan_ctx, kt, kb):
+    L = I.lib()
+    n = 1 << 20
+
+    def ws(opts, segs=0):
+        b = ctypes.c_size_t(0)
+        st = L.intsort_workspace_size(plan_ctx.handle, kt, 1, n, segs, ctypes.byref(opts), ctypes.byref(b))
+        return st, b.value
+
+    same_width = I.U32 if kb == 4 else I.U64
+    ref = ctypes.c_size_t(0)
+    assert L.intsort_workspace_size(plan_ctx.handle, same_width, 1, n, 0, ctypes.byref(I.make_options()),
+                                    ctypes.byref(ref)) == I.OK
+    assert ws(I.make_options()) == (I.OK, ref.value)
+    assert ws(I.make_options(digit_bits=11))[0] == I.ERR_UNSUPPORTED
+    assert ws(I.make_options(digit_bits=4))[0] == I.ERR_UNSUPPORTED
+    assert ws(I.make_options("bucket"))[0] == I.ERR_UNSUPPORTED
+    assert ws(I.make_options(), segs=4)[0] == I.ERR_UNSUPPORTED
+    assert _call_sort(plan_ctx, kt=kt, opts=I.make_options("bucket")) == I.ERR_UNSUPPORTED
+    off = 0x200000
+    assert L.intsort_segmented_sort_keys(plan_ctx.handle, kt, 0x1000, 0x100000, 100, 1, off,
+                                         ctypes.byref(I.make_options()), 0x1000000, 1 << 30,
+                                         None) == I.ERR_UNSUPPORTED
+    mm = (ctypes.c_uint64 * 2)()
+    assert L.intsort_minmax(plan_ctx.handle, kt, 0x1000, 100, mm, None) == I.ERR_UNSUPPORTED
+    assert L.intsort_digit_histogram(plan_ctx.handle, kt, 0x1000, 100, 8, 0x2000, 0x1000000, 1 << 20,
+                                     None) == I.ERR_UNSUPPORTED
+    assert _call_sort(plan_ctx, kt=6) == I.ERR_INVALID_ARGUMENT

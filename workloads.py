@@ -234,6 +234,50 @@ def config3_pairs(variant: str, n: int):
     return keys, np.arange(n, dtype=np.uint32)
 
 
+def signed_keys(n: int, width: int, seed: int, spread_bits: int | None = None) -> np.ndarray:
+    """Two's-complement keys (int32 or int64) from stream 5 of ``seed``: the
+    full range, or uniform on [-2^b, 2^b) for ``spread_bits`` = b < width."""
+    r = u64_stream(seed, 5, n)
+    if spread_bits is None:
+        u = r if width == 64 else (r >> np.uint64(32)).astype(np.uint32)
+        return u.view(np.int64 if width == 64 else np.int32)
+    v = (r >> np.uint64(63 - spread_bits)).astype(np.int64) - (1 << spread_bits)
+    return v.astype(np.int64 if width == 64 else np.int32)
+
+
+def ieee_keys(n: int, width: int, seed: int, special_share: int = 16) -> np.ndarray:
+    """IEEE 754 keys (float32 or float64).  For key i, stream 6 gives r and
+    stream 7 gives q.  One key in ``special_share`` (r >> 60 == 0 when the
+    share is 16) is a special value chosen by q >> 61: +-0, +-inf, a NaN of
+    either sign with payload q (nonzero), a subnormal of either sign; the
+    rest are (-1)^s 2^e (1 + f) with s = bit 0 of r, e uniform on
+    [-E, E] (E = 60 for float32, 500 for float64) and f from q.  Every ninth
+    key repeats the key four places earlier, so equal keys occur."""
+    ut, ft = (np.uint32, np.float32) if width == 32 else (np.uint64, np.float64)
+    mant = 23 if width == 32 else 52
+    expo = 0x7F800000 if width == 32 else 0x7FF0000000000000
+    sign = np.uint64(1) << np.uint64(width - 1)
+    E = 60 if width == 32 else 500
+    r = u64_stream(seed, 6, n)
+    q = u64_stream(seed, 7, n)
+    s = (r & np.uint64(1)).astype(np.float64)
+    e = ((r >> np.uint64(1)) % np.uint64(2 * E + 1)).astype(np.int64) - E
+    f = (q >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    out = (np.where(s == 1, -1.0, 1.0) * np.ldexp(1.0 + f, e)).astype(ft).view(ut).astype(np.uint64)
+    special = ((r >> np.uint64(32)) % np.uint64(special_share)) == 0
+    kind = q >> np.uint64(61)
+    payload = (q & np.uint64((1 << mant) - 1)) | np.uint64(1)
+    neg = np.where((q >> np.uint64(60)) & np.uint64(1) == 1, sign, np.uint64(0))
+    spec = np.select([kind == 0, kind == 1, kind == 2, kind == 3, kind < 6],
+                     [np.uint64(0), sign, np.uint64(expo), np.uint64(expo) | sign,
+                      np.uint64(expo) | payload | neg],
+                     default=payload | neg)
+    out = np.where(special, spec, out).astype(ut)
+    rep = np.arange(9, n, 9)
+    out[rep] = out[rep - 4]
+    return out.view(ft)
+
+
 def log_uniform_sizes(count: int, seed: int, lo: int, hi_exp_base: int) -> np.ndarray:
     """floor(lo * base^u) with u = (r >> 11) / 2^53 from stream 0 of seed."""
     u = (u64_stream(seed, 0, count) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
