@@ -38,6 +38,10 @@ def _workloads():
     w = {"uniform_u32_100M_radix_r8": ("plain", dict(dist=0, n=100_000_000, algo="radix", bits=8, B=0))}
     w["config1_u32_1M_radix_r8"] = ("plain", dict(dist=0, n=1_000_000, algo="radix", bits=8, B=0))
     w["config1_u32_1M_bucket_B1024"] = ("plain", dict(dist=0, n=1_000_000, algo="bucket", bits=8, B=1024))
+    for e, n in ((6, 1_000_000), (7, 10_000_000), (8, 100_000_000)):
+        w[f"uniform_u32_1e{e}_msd_r8"] = ("plain", dict(dist=0, n=n, algo="msd", bits=8, B=0))
+    w["signed_i32_100M_radix_r8"] = ("plain", dict(dist=0, n=100_000_000, algo="radix", bits=8, B=0, kind="i32"))
+    w["ieee_f32_100M_radix_r8"] = ("plain", dict(dist=0, n=100_000_000, algo="radix", bits=8, B=0, kind="f32"))
     for d, name in enumerate(DISTS):
         w[f"config2_{name}_u32_100M_radix_r8"] = ("plain", dict(dist=d, n=100_000_000, algo="radix", bits=8, B=0))
         w[f"config2_{name}_u32_100M_bucket_B1024"] = ("plain", dict(dist=d, n=100_000_000, algo="bucket", bits=8,
@@ -158,6 +162,23 @@ def _line(metric, value, unit, ms, steps, warmup, dtype, config, roofline=None, 
     return d
 
 
+def _sorted_permutation(keys_h, out_h):
+    """The output holds the input's bit patterns and is nondecreasing: unsigned
+    keys against numpy's sort; signed keys by value; IEEE keys by their
+    totalOrder rank (sign-magnitude bits mapped to a monotone unsigned)."""
+    import numpy as np
+    ut = np.uint32 if keys_h.dtype.itemsize == 4 else np.uint64
+    if keys_h.dtype.kind == "u":
+        return bool(np.array_equal(out_h, np.sort(keys_h)))
+    same = np.array_equal(np.sort(out_h.view(ut)), np.sort(keys_h.view(ut)))
+    if keys_h.dtype.kind == "i":
+        return bool(same and np.all(out_h[1:] >= out_h[:-1]))
+    b = out_h.view(ut).astype(np.uint64)
+    sign = np.uint64(1) << np.uint64(8 * keys_h.dtype.itemsize - 1)
+    rank = np.where(b & sign != 0, (sign - np.uint64(1)) - (b & (sign - np.uint64(1))), b | sign)
+    return bool(same and np.all(rank[1:] >= rank[:-1]))
+
+
 def run_plain(name, p, args):
     import numpy as np
     import torch
@@ -166,8 +187,15 @@ def run_plain(name, p, args):
     from paper_1206_3511_amd import intsort as I
 
     n, algo, bits, B = p["n"], p["algo"], p["bits"], p["B"]
-    print(f"bench[{name}]: generating {n} keys ({DISTS[p['dist']]})", file=sys.stderr, flush=True)
-    keys_h = workloads.config2_keys(p["dist"], n, seed=0 if p["dist"] == 0 else None)
+    kind = p.get("kind", "u32")
+    print(f"bench[{name}]: generating {n} keys ({DISTS[p['dist']] if kind == 'u32' else kind})",
+          file=sys.stderr, flush=True)
+    if kind == "i32":
+        keys_h = workloads.signed_keys(n, 32, seed=0)
+    elif kind == "f32":
+        keys_h = workloads.ieee_keys(n, 32, seed=0)
+    else:
+        keys_h = workloads.config2_keys(p["dist"], n, seed=0 if p["dist"] == 0 else None)
     keys = torch.from_numpy(keys_h).to("cuda:0")
     out = torch.empty_like(keys)
     ctx = I.context(0)
@@ -192,19 +220,21 @@ def run_plain(name, p, args):
         roof = _roofline("k_onesweep<BucketDigit> (one bucket-scatter pass)", per_pass,
                          avg.get("bucket_scatter", float("nan")),
                          {"kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()}})
-    ok = bool(np.array_equal(out.cpu().numpy(), np.sort(keys_h)))
+    ok = _sorted_permutation(keys_h, out.cpu().numpy())
     cpu = None
     if not args.no_cpu_baseline and name == "uniform_u32_100M_radix_r8":
         cpu = cpu_baseline(keys_h, algo, bits, B, args)
+    tname = {"u32": "uint32", "i32": "int32", "f32": "float32"}[kind]
     metric = "Gkeys/s at 100M uint32 (LSD radix, 8-bit digits)" if name == "uniform_u32_100M_radix_r8" else \
-        f"Gkeys/s ({algo}, {n} uint32 keys)"
+        f"Gkeys/s ({algo}, {n} {tname} keys)"
     mem = _memory(4, False, n, algo=algo, digit_bits=bits, num_buckets=B)
-    return _line(metric, value, "Gkeys/s", ms, args.steps, args.warmup, "u32",
-                 {"workload": name, "n": n, "distribution": DISTS[p["dist"]], "algo": algo, "digit_bits": bits,
-                  "num_buckets": B or None}, roof, cpu, output_matches_library_sort=ok, memory=mem)
+    return _line(metric, value, "Gkeys/s", ms, args.steps, args.warmup, kind,
+                 {"workload": name, "n": n, "distribution": DISTS[p["dist"]] if kind == "u32" else kind,
+                  "algo": algo, "digit_bits": bits, "num_buckets": B or None}, roof, cpu,
+                 output_matches_library_sort=ok, memory=mem)
 
 
-# section 4, Table 1 of the paper: seconds on its i5 laptop, one thread, by
+# section 3.2, Table 1 of the paper: seconds on its i5 laptop, one thread, by
 # (case, n) for RADIX sort and bucket sort; context for the case lines only
 PAPER_TABLE1 = {
     "radix": {1: (1.78, 17.66, 176.84), 2: (1.88, 18.93, 174.85), 3: (1.86, 17.69, 178.68),
@@ -239,14 +269,14 @@ def run_paper(name, p, args):
     kind = "pass" if algo == "radix" else "bucket_scatter"
     roof = _roofline("k_onesweep (one pass)" if algo == "radix" else "k_onesweep<BucketDigit> (one scatter pass)",
                      2 * n * 4, avg.get(kind, float("nan")), {"kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()}})
-    ok = bool(np.array_equal(out.cpu().numpy(), np.sort(keys_h)))
+    ok = _sorted_permutation(keys_h, out.cpu().numpy())
     sec = PAPER_TABLE1[algo][case][{10**6: 0, 10**7: 1, 10**8: 2}[n]]
     return _line(f"Gkeys/s (paper case {case}, {algo})", value, "Gkeys/s", ms, steps, 1, "u32",
                  {"workload": name, "case": case, "n": n, "M": M, "algo": algo,
                   "buckets": n if algo == "bucket" else None, "declared_range": [0, M] if algo == "bucket" else None},
                  roof, None, output_matches_library_sort=ok,
                  paper={"seconds": sec, "Gkeys_per_s": round(n / sec / 1e9, 7),
-                        "machine": "Intel i5 laptop, one thread (section 4)"},
+                        "machine": "Intel i5 laptop, one thread (section 3.1)"},
                  memory=_memory(4, False, n, **opts))
 
 

@@ -80,7 +80,17 @@ typedef enum intsort_key_type {
 
 typedef enum intsort_algo {
     INTSORT_RADIX_LSD = 0, /* Algorithm 4 over a stable per-digit counting sort */
-    INTSORT_BUCKET = 1     /* Algorithm 2: range, bucket scatter, per-bucket sort */
+    INTSORT_BUCKET = 1,    /* Algorithm 2: range, bucket scatter, per-bucket sort */
+    INTSORT_RADIX_MSD = 2  /* most significant digit first (section 2.5's other
+                              variant): one stable counting-sort pass on the
+                              top r = digit_bits bits of the key, then every one
+                              of the 2^r buckets sorted on its remaining bits,
+                              least significant digit first.  This is bucket
+                              sort over the declared range [0, 2^key_bits - 1]
+                              with 2^r buckets, and takes its options
+                              (max_passes 1 stops after the top-digit pass);
+                              num_buckets is ignored, key_bound must be 0.
+                              Unsigned keys only. */
 } intsort_algo;
 
 /* option flags */

@@ -47,9 +47,19 @@ intsort_status read_opts(const intsort_options *in, intsort_key_type kt, intsort
         if (in->struct_size != sizeof(intsort_options)) return INTSORT_ERR_INVALID_ARGUMENT;
         *out = *in;
     }
-    if (out->algo != INTSORT_RADIX_LSD && out->algo != INTSORT_BUCKET) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (out->algo != INTSORT_RADIX_LSD && out->algo != INTSORT_BUCKET && out->algo != INTSORT_RADIX_MSD)
+        return INTSORT_ERR_INVALID_ARGUMENT;
     if (out->digit_bits == 0) out->digit_bits = 8;
     if (out->digit_bits != 4 && out->digit_bits != 8 && out->digit_bits != 11) return INTSORT_ERR_UNSUPPORTED;
+    if (out->algo == INTSORT_RADIX_MSD) {
+        // the top r bits of the key are the bucket index floor(k * 2^r / 2^W)
+        // of bucket sort over the declared range [0, 2^W - 1]
+        if (out->key_bound != 0 || !unsigned_kt(kt)) return out->key_bound ? INTSORT_ERR_INVALID_ARGUMENT
+                                                                           : INTSORT_ERR_UNSUPPORTED;
+        out->algo = INTSORT_BUCKET;
+        out->num_buckets = 1u << out->digit_bits;
+        out->key_bound = kt == INTSORT_U64 ? ~0ull : 0xffffffffull;
+    }
     // signed and floating-point keys: radix sort with 8-bit digits only
     if (!unsigned_kt(kt) && (out->algo != INTSORT_RADIX_LSD || out->digit_bits != 8)) return INTSORT_ERR_UNSUPPORTED;
     if (out->num_buckets == 0) out->num_buckets = kt == INTSORT_U64 ? 65536u : 1024u;

@@ -27,7 +27,7 @@ ERR_INTERNAL = 7
 ERR_NOT_READY = 8
 
 U32, U64, I32, I64, F32, F64 = 0, 1, 2, 3, 4, 5
-RADIX, BUCKET = 0, 1
+RADIX, BUCKET, MSD = 0, 1, 2
 FLAG_NO_PASS_SKIP = 0x1
 
 EXPORTED = (
@@ -136,7 +136,7 @@ def make_options(algo: str | int = "radix", digit_bits: int = 0, num_buckets: in
                  key_bound: int = 0) -> Options:
     o = Options()
     lib().intsort_default_options(ctypes.byref(o))
-    o.algo = algo if isinstance(algo, int) else {"radix": RADIX, "bucket": BUCKET}[algo]
+    o.algo = algo if isinstance(algo, int) else {"radix": RADIX, "bucket": BUCKET, "msd": MSD}[algo]
     o.digit_bits = digit_bits
     o.num_buckets = num_buckets
     o.lds_cutoff = lds_cutoff

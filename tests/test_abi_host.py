@@ -143,3 +143,24 @@ def test_signed_and_float_keys_take_radix_with_8bit_digits(plan_ctx, kt, kb):
     assert L.intsort_digit_histogram(plan_ctx.handle, kt, 0x1000, 100, 8, 0x2000, 0x1000000, 1 << 20,
                                      None) == I.ERR_UNSUPPORTED
     assert _call_sort(plan_ctx, kt=6) == I.ERR_INVALID_ARGUMENT
+
+
+def test_msd_is_bucket_sort_over_the_full_range(plan_ctx):
+    L = I.lib()
+    n = 1 << 22
+    for kt, top in ((I.U32, (1 << 32) - 1), (I.U64, (1 << 64) - 1)):
+        for r in (4, 8, 11):
+            a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+            assert L.intsort_workspace_size(plan_ctx.handle, kt, 1, n, 0,
+                                            ctypes.byref(I.make_options("msd", digit_bits=r, num_buckets=77)),
+                                            ctypes.byref(a)) == I.OK
+            assert L.intsort_workspace_size(plan_ctx.handle, kt, 1, n, 0,
+                                            ctypes.byref(I.make_options("bucket", num_buckets=1 << r,
+                                                                        key_bound=top)),
+                                            ctypes.byref(b)) == I.OK
+            assert a.value == b.value
+    assert _call_sort(plan_ctx, opts=I.make_options("msd", key_bound=5)) == I.ERR_INVALID_ARGUMENT
+    assert _call_sort(plan_ctx, kt=I.I32, opts=I.make_options("msd")) == I.ERR_UNSUPPORTED
+    bad = I.make_options()
+    bad.algo = 3
+    assert _call_sort(plan_ctx, opts=bad) == I.ERR_INVALID_ARGUMENT

@@ -1,5 +1,5 @@
 """Device memory of one sort call (the analogue of the paper's memory table,
-section 4, Table 2): input, output and the workspace the library asks for.
+section 3.2, Table 2): input, output and the workspace the library asks for.
 Planning context only, no GPU."""
 import pytest
 

@@ -403,3 +403,20 @@ def test_unsigned_order_equals_radix():
     ek, ev = stable_ref(k, v)
     np.testing.assert_array_equal(got_k, ek)
     np.testing.assert_array_equal(got_v, ev)
+
+
+@pytest.mark.parametrize("dtype,r", [(np.uint32, 8), (np.uint32, 4), (np.uint64, 11), (np.uint64, 8)])
+def test_full_declared_range_buckets_are_top_bits(dtype, r):
+    """With the declared range [0, 2^W - 1] and 2^r buckets the bucket of k is
+    floor(k * 2^r / 2^W) = k >> (W - r), its top r bits: the scatter is the
+    stable partition on the most significant digit."""
+    n = 4000
+    k = rand_keys(n, dtype)
+    W = 8 * k.dtype.itemsize
+    res = oracle.bucket(k, np.arange(n, dtype=np.uint32), num_buckets=1 << r, key_bound=(1 << W) - 1,
+                        want_intermediates=True)
+    top = (k >> k.dtype.type(W - r)).astype(np.int64)
+    order = np.argsort(top, kind="stable")
+    np.testing.assert_array_equal(res.scat_keys, k[order])
+    np.testing.assert_array_equal(res.scat_vals, order.astype(np.uint32))
+    np.testing.assert_array_equal(res.counts.astype(np.int64), np.bincount(top, minlength=1 << r))

@@ -66,7 +66,7 @@ def test_segmented_keys_layout():
 
 
 def test_paper_cases_shapes_and_checksums():
-    """The six input cases of section 4: range, order, repeated value, and
+    """The six input cases of section 3.1: range, order, repeated value, and
     the recorded checksums of their first 2^16-key instances."""
     gold = json.load(open(os.path.join(HERE, "golden", "input_checksums.json")))["paper_cases"]
     n = 1 << 16

@@ -147,7 +147,7 @@ def config2_keys(dist: int | str, n: int, seed: int | None = None) -> np.ndarray
     raise ValueError(f"unknown distribution {dist}")
 
 
-# ---- the paper's six input cases (section 4): n keys in [0, M]
+# ---- the paper's six input cases (section 3.1): n keys in [0, M]
 
 PAPER_CASE_M = {1: 10**6, 2: 10**6, 3: 10**6, 4: 10**4, 5: 10**8, 6: 10**6}
 
@@ -180,7 +180,7 @@ def _distinct_below(seed: int, count: int, U: int) -> np.ndarray:
 
 
 def paper_case(case: int, n: int, seed: int | None = None):
-    """(keys, M) for input case 1..6 of section 4 at size n, uint32 keys:
+    """(keys, M) for input case 1..6 of section 3.1 at size n, uint32 keys:
       1  uniform in [0, M], M = 10^6
       2  case 1 sorted
       3  case 1 sorted, then n/20 positions (stream 1) take new uniform values
