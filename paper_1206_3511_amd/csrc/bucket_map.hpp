@@ -22,7 +22,9 @@ struct BucketMap {
     uint32_t buckets;     // B >= 1
     double scale;         // B / R in double precision (64-bit keys)
     uint64_t inv;         // floor((2^64 - 1) / R) (32-bit keys, R <= 2^32)
+    uint64_t mul;         // floor(2^64 B / R) + 1 when fast32
     bool full64;          // R == 2^64
+    bool fast32;          // R <= 2^32 and B < R: 32-bit keys use mul
 };
 
 __device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, uint32_t B)
@@ -36,16 +38,43 @@ __device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, u
     const double R = m.full64 ? 18446744073709551616.0 : (double)m.range_m1 + 1.0;
     m.scale = (double)B / R;
     m.inv = m.full64 ? 1ull : ~0ull / (m.range_m1 + 1);
+    m.fast32 = !m.full64 && m.range_m1 <= 0xffffffffull && (uint64_t)B <= m.range_m1;
+    m.mul = 0;
+    if (m.fast32) {
+        // 2^64 = q R + r with 0 <= r < R, from floor((2^64 - 1) / R)
+        const uint64_t Rr = m.range_m1 + 1;
+        uint64_t q = m.inv, r = ~0ull - m.inv * Rr;
+        if (r == Rr - 1) {
+            q += 1;
+            r = 0;
+        } else {
+            r += 1;
+        }
+        // floor(2^64 B / R) = q B + floor(r B / R); below 2^64 because B < R
+        m.mul = q * B + (r * B) / Rr + 1;
+    }
     return m;
 }
 
-// b(k) for 32-bit keys.  num = (k - min) * B is below 2^62; with
-// inv = floor((2^64 - 1) / R) the estimate floor(num * inv / 2^64) is either
-// the exact quotient or one less (num * inv / 2^64 lies below num / R and
-// within 2 num / 2^64 < 1/2 of it), so one remainder check makes it exact.  The result is clamped
-// so that a key outside [min, max] cannot index past B.
+// b(k) for 32-bit keys.  With B < R one fixed-point product gives it (below).
+// Otherwise num = (k - min) * B is below 2^62; with inv = floor((2^64 - 1) / R)
+// the estimate floor(num * inv / 2^64) is either the exact quotient or one
+// less (num * inv / 2^64 lies below num / R and within 2 num / 2^64 < 1/2 of
+// it), so one remainder check makes it exact.  The result is clamped so that
+// a key outside [min, max] cannot index past B.
 __device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint32_t k)
 {
+    if (m.fast32) {
+        // b(k) = floor(x * mul / 2^64) with mul = floor(2^64 B / R) + 1: the
+        // product exceeds x B / R by less than x / 2^64 < 2^-32 <= 1 / R,
+        // while x B / R sits at least 1/R below the next integer, so the
+        // floor is exact.  x * mul / 2^64 is taken as
+        // (x * mul_hi + floor(x * mul_lo / 2^32)) / 2^32, which fits 64 bits.
+        const uint32_t x = k - (uint32_t)m.mn;
+        const uint64_t t = (uint64_t)x * (m.mul >> 32) + __umulhi(x, (uint32_t)m.mul);
+        const uint32_t q = (uint32_t)(t >> 32);
+        return q < m.buckets ? q : m.buckets - 1;
+    }
     const uint64_t x = (uint64_t)(k - (uint32_t)m.mn);
     const uint64_t num = x * (uint64_t)m.buckets;
     const uint64_t R = m.range_m1 + 1;   // <= 2^32 for 32-bit keys
