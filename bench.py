@@ -63,18 +63,70 @@ def _workloads():
 WORKLOADS = _workloads()
 
 
+_STEPS_MS = []   # per-step times of the last _timed call
+
+
 def _timed(fn, steps, warmup):
+    """Mean milliseconds per step over exactly `steps` steps after `warmup`
+    untimed ones; an event after every step also gives each step's time."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
         fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    _STEPS_MS[:] = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / steps
+
+
+def _step_stats():
+    import statistics
+    if not _STEPS_MS:
+        return {}
+    return {"ms_median": round(statistics.median(_STEPS_MS), 5), "ms_min": round(min(_STEPS_MS), 5)}
+
+
+def _copy_ceiling(t):
+    """Read+write bandwidth of a plain device copy of `t` (torch's copy
+    kernel), the practical ceiling of a streaming pass, in GB/s."""
+    import torch
+    dst = torch.empty_like(t)
+    for _ in range(2):
+        dst.copy_(t)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    s.record()
+    for _ in range(reps):
+        dst.copy_(t)
     e.record()
     torch.cuda.synchronize()
-    return s.elapsed_time(e) / steps
+    ms = s.elapsed_time(e) / reps
+    del dst
+    return round(2 * t.numel() * t.element_size() / (ms * 1e-3) / 1e9, 1)
+
+
+def _cold_ms(fn, steps):
+    """Per-sort time when a 512 MB write has just evicted the caches (L2 and
+    the 256 MB last-level cache) before each sort: median and minimum."""
+    import statistics
+    import torch
+    flush = torch.empty(1 << 27, dtype=torch.int32, device="cuda:0")
+    times = []
+    for _ in range(steps):
+        flush.fill_(1)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        torch.cuda.synchronize()
+        times.append(s.elapsed_time(e))
+    del flush
+    return {"ms_cold_median": round(statistics.median(times), 5), "ms_cold_min": round(min(times), 5)}
 
 
 def _kernel_avgs(ctx, fn, steps):
@@ -158,6 +210,7 @@ def _line(metric, value, unit, ms, steps, warmup, dtype, config, roofline=None, 
     d = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
          "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
          "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu}
+    d.update(_step_stats())
     d.update(extra)
     return d
 
@@ -202,9 +255,15 @@ def run_plain(name, p, args):
     opts = dict(algo=algo, digit_bits=bits, num_buckets=B)
     fn = lambda: I.sort(keys, out=out, **opts)  # noqa: E731
     ms = _timed(fn, args.steps, args.warmup)
+    steps_ms = list(_STEPS_MS)
     value = n / (ms * 1e-3) / 1e9
     print(f"bench[{name}]: {ms:.4f} ms/sort, {value:.2f} Gkeys/s", file=sys.stderr, flush=True)
     avg = _kernel_avgs(ctx, fn, args.steps)
+    # a 4 MB input stays in the 256 MB last-level cache between sorts, so
+    # small sorts also report times with the caches flushed first
+    cold = _cold_ms(fn, args.steps) if n * 4 <= (1 << 26) else {}
+    copy_gbs = _copy_ceiling(keys) if name == "uniform_u32_100M_radix_r8" else None
+    _STEPS_MS[:] = steps_ms
     w = 4
     if algo == "radix":
         passes = -(-32 // bits)
@@ -212,6 +271,9 @@ def run_plain(name, p, args):
         total = n * w + passes * per_pass
         roof = _roofline("k_onesweep (one digit pass)", per_pass, avg.get("pass", float("nan")),
                          {"traffic": measured_traffic() if name == "uniform_u32_100M_radix_r8" else None,
+                          "copy_ceiling_gbs": copy_gbs,
+                          "frac_of_copy": (round(per_pass / (avg.get("pass", float("nan")) * 1e-3) / 1e9 / copy_gbs, 4)
+                                           if copy_gbs else None),
                           "kernel_avg_ms": {k: round(x, 5) for k, x in avg.items()},
                           "sort_level_frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "algorithmic_bytes_per_sort": total})
@@ -231,7 +293,7 @@ def run_plain(name, p, args):
     return _line(metric, value, "Gkeys/s", ms, args.steps, args.warmup, kind,
                  {"workload": name, "n": n, "distribution": DISTS[p["dist"]] if kind == "u32" else kind,
                   "algo": algo, "digit_bits": bits, "num_buckets": B or None}, roof, cpu,
-                 output_matches_library_sort=ok, memory=mem)
+                 output_matches_library_sort=ok, memory=mem, **cold)
 
 
 # section 3.2, Table 1 of the paper: seconds on its i5 laptop, one thread, by
@@ -288,6 +350,12 @@ def cpu_baseline(keys_h, algo, bits, B, args):
     sample = keys_h[:m].copy()
     print(f"bench: CPU oracle on {m} keys", file=sys.stderr, flush=True)
     runs, spent, best = 0, 0.0, float("inf")
+    # one core, the first this process may use, for the whole timing
+    try:
+        old_aff = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(old_aff)})
+    except (AttributeError, OSError):
+        old_aff = None
     while runs < 1 or (spent < args.cpu_seconds and runs < 20):
         t0 = time.perf_counter()
         if algo == "radix":
@@ -298,8 +366,17 @@ def cpu_baseline(keys_h, algo, bits, B, args):
         spent += dt
         best = min(best, dt)
         runs += 1
+    if old_aff is not None:
+        os.sched_setaffinity(0, old_aff)
     per = spent / runs
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": round(m / per / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_cores": os.cpu_count(),
             "sample": f"{'all' if m == n else 'first'} {m} keys of the same input, single-threaded oracle "
                       f"{algo} sort repeated {runs} times ({spent:.1f} s, mean {per:.3f} s, best {best:.3f} s)"}
 

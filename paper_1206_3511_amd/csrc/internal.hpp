@@ -81,7 +81,7 @@ struct RadixLayout {
     uint64_t n;
     uint64_t num_tiles;
     uint64_t status_words;   // words of each of the two status arrays
-    size_t tmp_keys, tmp_vals, hist, excl, plan, counters, status0, status1, total;
+    size_t tmp_keys, tmp_vals, hist, excl, plan, counters, status0, status1, tile_offs, chunk_offs, total;
 };
 
 RadixGeom radix_geometry(int key_bytes, int bits);

@@ -134,6 +134,7 @@ struct TileInfo {
     uint32_t first_tile;  // id of the first tile of the tile's segment
     uint32_t base;        // index of the segment's first key
     const uint32_t *excl; // exclusive digit offsets inside the segment
+    const uint32_t *excl2; // offsets added to excl when not null
     const void *in;       // the three key buffers the indices refer to
     void *out;
     void *tmp;
@@ -157,6 +158,33 @@ struct PlainTiles {
         return true;
     }
     // every tile runs the pass with the buffers of the pass's plan
+    __device__ bool route(const TileInfo &, uint32_t, uint32_t &, uint32_t &) const { return true; }
+    __device__ bool missing_is_error() const { return true; }
+    __device__ uint32_t listed() const { return num_tiles; }
+};
+
+// tiles of one array whose digit offsets were found before the pass: the
+// histogram kernel counted every tile's digits and a scan over the tiles
+// turned the counts into offsets, so no tile looks back (each one is the
+// first of its own run of tiles)
+struct ScannedTiles {
+    uint32_t n, num_tiles;
+    const uint32_t *offs;        // [tile][radix]: the tile's digit offsets inside its chunk
+    const uint32_t *chunk_offs;  // [chunk][radix]: where each chunk's run of each digit starts
+    uint32_t radix;
+    uint32_t tiles_per_chunk;
+    template <int TILE>
+    __device__ __forceinline__ bool get(uint32_t t, TileInfo &ti) const
+    {
+        if (t >= num_tiles) return false;
+        ti.start = t * (uint32_t)TILE;
+        ti.count = min((uint32_t)TILE, n - ti.start);
+        ti.first_tile = t;
+        ti.base = 0;
+        ti.excl = offs + (uint64_t)t * radix;
+        ti.excl2 = chunk_offs + (uint64_t)(t / tiles_per_chunk) * radix;
+        return true;
+    }
     __device__ bool route(const TileInfo &, uint32_t, uint32_t &, uint32_t &) const { return true; }
     __device__ bool missing_is_error() const { return true; }
     __device__ uint32_t listed() const { return num_tiles; }
@@ -483,6 +511,7 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     __syncthreads();
     const uint32_t tile = s_tile;
     TileInfo ti;
+    ti.excl2 = nullptr;
     ti.in = a.in;
     ti.out = a.out;
     ti.tmp = a.tmp;
@@ -610,7 +639,7 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
                 prefix = look_back<RADIX>(status, tflag, tile, ti.first_tile, d, &a.counters[CTR_ERROR]);
                 store_agent(&status[(uint64_t)tile * RADIX + d], FLAG_INC | (prefix + tcnt[i]));
             }
-            s_gbase[d] = ti.base + ti.excl[d] + prefix - texcl[i];
+            s_gbase[d] = ti.base + ti.excl[d] + (ti.excl2 ? ti.excl2[d] : 0u) + prefix - texcl[i];
             store_agent(&status_next[(uint64_t)tile * RADIX + d], 0u);
         }
     }

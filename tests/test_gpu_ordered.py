@@ -113,3 +113,13 @@ def test_ordered_empty_and_unsupported():
             I.sort(k, algo="bucket")
         with pytest.raises(RuntimeError):
             I.sort(k, algo="radix", digit_bits=11)
+
+
+@pytest.mark.parametrize("kind", ["int32", "float32"])
+def test_ordered_scanned_first_pass(kind):
+    """32-bit sorts of at least 2048 tiles take the first pass without a
+    look-back; signed and IEEE keys through that path."""
+    n = 2048 * 16384 + 777
+    print(f"ordered scanned first pass n={n} {kind}", flush=True)
+    keys = workloads.signed_keys(n, 32, seed=5) if kind == "int32" else workloads.ieee_keys(n, 32, seed=5)
+    _check(keys)

@@ -146,3 +146,25 @@ def test_config2_full_size(dist):
     ref = oracle.radix_lsd(keys, r=8).keys
     np.testing.assert_array_equal(out, ref)
     assert I.device_error(0) == 0
+
+
+# 32-bit key sorts of at least 2048 tiles take the first pass without a
+# look-back: its per-tile digit offsets come from the histogram kernel and a
+# scan over chunks of tiles
+SCANNED_N = 2048 * 16384 + 4099
+
+
+@pytest.mark.parametrize("case", ["uniform", "low_byte_constant", "small_range"])
+def test_scanned_first_pass(case):
+    print(f"scanned first pass n={SCANNED_N} case={case}", flush=True)
+    keys = workloads.config2_keys(0, SCANNED_N, seed=21)
+    if case == "low_byte_constant":
+        keys = (keys & np.uint32(0xFFFFFF00)) | np.uint32(0x5A)   # pass 0 skipped: look-back from pass 1
+    elif case == "small_range":
+        keys = keys >> np.uint32(22)                             # passes 2 and 3 skipped
+    out = host(I.sort(dev(keys)))
+    np.testing.assert_array_equal(out, oracle.radix_lsd(keys, r=8).keys)
+    assert I.device_error(0) == 0
+    # the intermediate array after the first pass alone
+    one = host(I.sort(dev(keys), max_passes=1))
+    np.testing.assert_array_equal(one, oracle.radix_lsd(keys, r=8, want_passes=True).pass_keys[0])
