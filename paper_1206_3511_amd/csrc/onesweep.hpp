@@ -545,7 +545,13 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     const uint32_t valid = ti.count;
     const bool first = tile == ti.first_tile;
 
-    // ---- load: wave-striped, so (wave, item, lane) order is index order
+    // ---- load: wave-striped, so (wave, item, lane) order is index order.
+    // With 32-bit keys, keys, values and ranks in registers at once would not
+    // fit in 128 VGPRs (two workgroups per CU): their values are loaded after
+    // the keys have gone to LDS, and each staged key keeps only its digit
+    // (four to a word) to find its value's destination
+    constexpr bool COMPACT = PAIRS && sizeof(K) == 4;
+    static_assert(!COMPACT || BITS <= 8, "digits pack four to a word");
     K k[IPT];
     uint32_t v[PAIRS ? IPT : 1];
     const uint32_t lofs = wave * (IPT * WAVE) + lane;   // tile-local index of item 0
@@ -553,18 +559,18 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     if (valid == (uint32_t)TILE) {
         // one base address per thread, item offsets as immediates
         const K *sp = src + wofs;
-        const uint32_t *vp = PAIRS ? vsrc + wofs : nullptr;
+        const uint32_t *vp = PAIRS && !COMPACT ? vsrc + wofs : nullptr;
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
             k[j] = sp[j * WAVE];
-            if (PAIRS) v[j] = vp[j * WAVE];
+            if (PAIRS && !COMPACT) v[j] = vp[j * WAVE];
         }
     } else {
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
             const bool in = lofs + j * WAVE < valid;
             k[j] = in ? src[wofs + j * WAVE] : dg.template pad<K>();
-            if (PAIRS) v[j] = in ? vsrc[wofs + j * WAVE] : 0u;
+            if (PAIRS && !COMPACT) v[j] = in ? vsrc[wofs + j * WAVE] : 0u;
         }
     }
     // keys past the end of the tile take the largest digit and so rank last
@@ -627,6 +633,17 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         rk[j] += s_wcnt[wave * RADIX + d];
         s_stage[rk[j]] = k[j];
     }
+    if constexpr (COMPACT) {
+        // the value loads complete during the look-back
+        if (valid == (uint32_t)TILE) {
+            const uint32_t *vp = vsrc + wofs;
+#pragma unroll
+            for (int j = 0; j < IPT; j++) v[j] = vp[j * WAVE];
+        } else {
+#pragma unroll
+            for (int j = 0; j < IPT; j++) v[j] = lofs + j * WAVE < valid ? vsrc[wofs + j * WAVE] : 0u;
+        }
+    }
 
     // ---- look-back: the counts of this digit in the earlier tiles of the
     // segment
@@ -650,18 +667,24 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     }
 
     // ---- contiguous runs of each digit go to their global offsets
-    uint32_t dest[PAIRS ? IPT : 1];
+    uint32_t dest[PAIRS && !COMPACT ? IPT : 1];   // where each staged key went
+    uint32_t dpk[COMPACT ? (IPT + 3) / 4 : 1];     // or its digit, four to a word
+    if (COMPACT)
+#pragma unroll
+        for (int q = 0; q < (IPT + 3) / 4; q++) dpk[q] = 0;
     bool bad = false;
 #pragma unroll
     for (int m = 0; m < IPT; m++) {
         const uint32_t i = m * NT + tid;
-        if (PAIRS) dest[m] = n;
+        if (PAIRS && !COMPACT) dest[m] = n;
         if (i < valid) {
             const K key = s_stage[i];
-            const uint32_t g = s_gbase[dg(key)] + i;
+            const uint32_t d = dg(key);
+            const uint32_t g = s_gbase[d] + i;
+            if (COMPACT) dpk[m / 4] |= d << (8 * (m % 4));
             if (g < n) {
                 dst[g] = key;
-                if (PAIRS) dest[m] = g;
+                if (PAIRS && !COMPACT) dest[m] = g;
             } else {
                 bad = true;
             }
@@ -677,7 +700,9 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
 #pragma unroll
         for (int m = 0; m < IPT; m++) {
             const uint32_t i = m * NT + tid;
-            if (i < valid && dest[m] < n) vdst[dest[m]] = s_v[i];
+            if (i >= valid) continue;
+            const uint32_t g = COMPACT ? s_gbase[(dpk[m / 4] >> (8 * (m % 4))) & 255u] + i : dest[m];
+            if (g < n) vdst[g] = s_v[i];
         }
     }
 }
