@@ -437,6 +437,7 @@ def run_batched(name, p, args):
     fn = lambda: I.segmented_sort(k, offs, out_keys=out, **choice)  # noqa: E731
     steps = max(1, args.steps // 4)
     ms = _timed(fn, steps, 1)
+    steps_ms = list(_STEPS_MS)
     value = N / (ms * 1e-3) / 1e9
     avg = _kernel_avgs(ctx, fn, steps)
     # the plain path: every array in its own buffer, one sort call each
@@ -447,6 +448,7 @@ def run_batched(name, p, args):
         for a, b in zip(arrs, outs):
             I.sort(a, out=b)
     ms_loop = _timed(loop, 1, 1)
+    _STEPS_MS[:] = steps_ms
     roof = _roofline("k_onesweep<SegTiles> (one digit pass of the large arrays)", 2 * N * 4,
                      avg.get("pass", float("nan")), {"kernel_avg_ms": {kk: round(x, 5) for kk, x in avg.items()}})
     return _line("Gkeys/s (batched segmented sort of 10,000 uint32 arrays)", value, "Gkeys/s", ms, steps, 1, "u32",
@@ -457,11 +459,12 @@ def run_batched(name, p, args):
                  memory=_memory(4, False, int(N), len(offsets) - 1, **choice))
 
 
-def serve_trace(I, pool, outbufs, trace, mode, sample_every=0):
+def serve_trace(I, pool, out_cap_bytes, trace, mode, sample_every=0):
     """Replays the trace through a server.  Requests arrive at their trace
-    times (open loop); each needs one of the preallocated output buffers, and
-    a request that finds none free waits for one (that wait counts in its
-    latency, which runs from arrival to the completion the driver observes).
+    times (open loop); each gets an output tensor of its own size, and a
+    request that would take the output memory in flight past `out_cap_bytes`
+    waits until completions free enough (that wait counts in its latency,
+    which runs from arrival to the completion the driver observes).
     Returns (throughput Gkeys/s, p50 s, p99 s, requests, keys, samples)."""
     import numpy as np
     import torch
@@ -469,7 +472,7 @@ def serve_trace(I, pool, outbufs, trace, mode, sample_every=0):
     t_arr, wid, nn, dd = trace
     max_batch, slots = (64, 2) if mode == "batched" else (1, 1)
     srv = I.Server(0, budget_bytes=64 << 30, max_batch=max_batch, slots=slots)
-    free = list(range(len(outbufs)))
+    inflight = 0
     lat, keys_done, live, samples = [], 0, {}, []
     R = len(t_arr)
     i = 0
@@ -477,24 +480,27 @@ def serve_trace(I, pool, outbufs, trace, mode, sample_every=0):
     first = last = None
     while i < R or live:
         now = time.perf_counter() - t0
-        while i < R and t_arr[i] <= now and free:
-            b = free.pop()
+        while i < R and t_arr[i] <= now:
             n = int(nn[i])
+            nbytes = n * int(wid[i])
+            if live and inflight + nbytes > out_cap_bytes:
+                break
             src = pool[(int(wid[i]), int(dd[i]))][:n]
-            out = outbufs[b].view(src.dtype)[:n]
+            out = torch.empty_like(src)
+            inflight += nbytes
             tk = srv.submit(src, out)
-            live[tk] = (i, b, out)
+            live[tk] = (i, nbytes, out)
             if first is None:
                 first = time.perf_counter()
             i += 1
         for tk, _ in srv.completed():
-            idx, b, out = live.pop(tk)
+            idx, nbytes, out = live.pop(tk)
             done = time.perf_counter()
             lat.append(done - (t0 + t_arr[idx]))
             keys_done += int(nn[idx])
             if sample_every and idx % sample_every == 0 and len(samples) < 40:
-                samples.append((idx, out.clone()))
-            free.append(b)
+                samples.append((idx, out))
+            inflight -= nbytes
             last = done
         time.sleep(0.0001)
     srv.drain()
@@ -521,13 +527,12 @@ def run_serving(name, p, args):
     for wdt in (4, 8):
         for d in range(7):
             pool[(wdt, d)] = workloads.device_keys(d, 1 << 26, 7000 + 10 * d + wdt, wdt, "cuda:0")
-    # output buffers: each holds the largest request (2^26 keys of 8 bytes)
-    outbufs = [torch.empty(1 << 26, dtype=torch.uint64, device="cuda:0") for _ in range(args.serve_buffers)]
     torch.cuda.synchronize()
+    out_cap = int(args.serve_out_gb * (1 << 30))
     res = {}
     for mode in ("batched", "plain"):
         print(f"bench[{name}]: {mode}", file=sys.stderr, flush=True)
-        thr, p50, p99, cnt, keys, samples = serve_trace(I, pool, outbufs, trace, mode,
+        thr, p50, p99, cnt, keys, samples = serve_trace(I, pool, out_cap, trace, mode,
                                                         sample_every=100 if mode == "batched" else 0)
         print(f"bench[{name}]: {mode}: {thr:.2f} Gkeys/s p50 {p50 * 1e3:.3f} ms p99 {p99 * 1e3:.3f} ms",
               file=sys.stderr, flush=True)
@@ -547,7 +552,7 @@ def run_serving(name, p, args):
     return _line("Gkeys/s served (Poisson 2000 req/s, uint32/uint64, 1K-64M keys)", b["gkeys_per_s"], "Gkeys/s",
                  float("nan"), 0, 0, "u32/u64",
                  {"workload": name, "rate_per_s": 2000, "seconds": seconds, "budget_gb": 64, "max_batch": 64,
-                  "slots": 2, "output_buffers": args.serve_buffers}, None, None, serving=res,
+                  "slots": 2, "output_cap_gb": args.serve_out_gb}, None, None, serving=res,
                  p50_ms=b["p50_ms"], p99_ms=b["p99_ms"], plain_path=res["plain"])
 
 
@@ -564,8 +569,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU oracle sort until this much time has passed")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving trace")
-    ap.add_argument("--serve-buffers", type=int, default=96,
-                    help="preallocated output buffers of 512 MB each for the serving trace")
+    ap.add_argument("--serve-out-gb", type=float, default=64.0,
+                    help="serving trace: output memory the requests in flight may hold")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB plain copy (for scaling hardware byte counters)")
     args = ap.parse_args()
@@ -588,6 +593,7 @@ def main():
         kind, p = WORKLOADS[name]
         fn = {"plain": run_plain, "pairs": run_pairs, "batched": run_batched, "serving": run_serving,
               "paper": run_paper}[kind]
+        _STEPS_MS.clear()
         print(json.dumps(fn(name, p, args)), flush=True)
         import torch
         torch.cuda.empty_cache()

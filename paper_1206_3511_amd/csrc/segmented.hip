@@ -39,8 +39,6 @@ struct SegWs {
     uint32_t *plan;
     uint32_t *lists;          // [NCLASS][list_stride]
     uint32_t list_stride;
-    uint32_t *slot_first;     // [slots] first tile id of every large segment
-    uint32_t *slot_ntiles;    // [slots]
     TileDesc *tiles;          // [tile_cap]
     uint32_t *tile_hist;      // [tile_cap][passes][256]
     uint32_t *seg_excl;       // [passes][slot_cap][256]
@@ -115,8 +113,6 @@ __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segm
         atomicOr(&w.counters[CTR_ERROR], DEVERR_BAD_TILE);
         return;
     }
-    w.slot_first[slot] = first;
-    w.slot_ntiles[slot] = nt;
     if (w.bufs) {
         const uint32_t toff = atomicAdd(&w.counters[CTR_SEG_TMP], m);
         SegBuf b;
@@ -139,7 +135,9 @@ __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segm
 }
 
 // per listed tile: the digit counts of every pass (one read of its keys);
-// also clears the tile's look-back words for the first pass
+// also clears the tile's look-back words for the first pass, and the first
+// tile of each segment clears the segment's digit totals, which
+// k_seg_slot_sum adds up next
 template <typename K>
 __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__restrict__ keys, SegWs w)
 {
@@ -149,6 +147,9 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
     if (t >= w.counters[CTR_SEG_TILES]) return;
     const TileDesc d = w.tiles[t];
     const K *kp = w.bufs ? static_cast<const K *>(w.bufs[d.slot].in) : keys;
+    if (t == d.first_tile)
+        for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS)
+            w.seg_excl[((uint64_t)(i / 256) * w.slot_cap + d.slot) * 256 + i % 256] = 0;
     for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS) s_h[i] = 0;
     for (uint32_t i = threadIdx.x; i < 256u; i += SEG_HIST_THREADS) w.status0[(uint64_t)t * 256 + i] = 0;
     if (threadIdx.x == 0) w.status0[(uint64_t)w.tile_cap * 256 + t] = 0;
@@ -176,7 +177,47 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
     for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS) out[i] = s_h[i];
 }
 
-// per large segment: sum its tiles' counts, exclusive scan per pass
+// Digit totals of every large segment: each workgroup adds up the counts of
+// SUM_TILES consecutive listed tiles (a segment's tiles have consecutive
+// ids), one thread per digit, and adds each segment's part into its totals
+// in seg_excl.  A segment of thousands of tiles is spread over many
+// workgroups instead of being walked by one.
+constexpr uint32_t SUM_TILES = 32;
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_seg_slot_sum(SegWs w)
+{
+    constexpr int PASSES = (int)sizeof(K);
+    const uint32_t listed = min(w.counters[CTR_SEG_TILES], w.tile_cap);
+    const uint32_t t0 = blockIdx.x * SUM_TILES;
+    if (t0 >= listed) return;
+    const uint32_t t1 = min(listed, t0 + SUM_TILES);
+    const uint32_t d = threadIdx.x;
+    uint32_t acc[PASSES];
+    auto flush = [&](uint32_t slot) {
+#pragma unroll
+        for (int p = 0; p < PASSES; p++) {
+            if (acc[p]) atomicAdd(&w.seg_excl[((uint64_t)p * w.slot_cap + slot) * 256 + d], acc[p]);
+            acc[p] = 0;
+        }
+    };
+#pragma unroll
+    for (int p = 0; p < PASSES; p++) acc[p] = 0;
+    uint32_t cur = w.tiles[t0].slot;
+    for (uint32_t t = t0; t < t1; t++) {
+        const uint32_t slot = w.tiles[t].slot;
+        if (slot != cur) {
+            flush(cur);
+            cur = slot;
+        }
+#pragma unroll
+        for (int p = 0; p < PASSES; p++) acc[p] += w.tile_hist[((uint64_t)t * PASSES + p) * 256 + d];
+    }
+    flush(cur);
+}
+
+// per large segment: exclusive scan of its digit totals per pass, and the
+// passes whose digit is not constant inside it
 template <typename K>
 __global__ __launch_bounds__(256) void k_seg_scan(SegWs w)
 {
@@ -185,12 +226,10 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegWs w)
     __shared__ uint32_t s_const;
     const uint32_t slot = blockIdx.x;
     if (slot >= w.counters[CTR_SEG_SLOTS] || slot >= w.slot_cap) return;
-    const uint32_t first = w.slot_first[slot], nt = w.slot_ntiles[slot];
     const uint32_t d = threadIdx.x;
     uint32_t mask = 0;
     for (int p = 0; p < PASSES; p++) {
-        uint32_t c = 0;
-        for (uint32_t t = 0; t < nt; t++) c += w.tile_hist[((uint64_t)(first + t) * PASSES + p) * 256 + d];
+        const uint32_t c = w.seg_excl[((uint64_t)p * w.slot_cap + slot) * 256 + d];
         if (d == 0) s_const = 0;
         uint32_t total;
         const uint32_t ex = block_exclusive_scan<256>(c, s_scan, &total);
@@ -259,8 +298,6 @@ static SegLayout seg_layout_typed(uint64_t n, uint64_t S, uint32_t cutoff_req)
     L.counters = take((size_t)CTR_WORDS * 4);
     L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
     L.lists = take((size_t)SegClasses<K>::NCLASS * S * 4);
-    L.slot_first = take((size_t)L.slot_cap * 4);
-    L.slot_ntiles = take((size_t)L.slot_cap * 4);
     L.tiles = take((size_t)L.tile_cap * sizeof(TileDesc));
     L.bufs = take((size_t)L.slot_cap * sizeof(SegBuf));
     L.tile_hist = take((size_t)L.tile_cap * PASSES * 256 * 4);
@@ -309,8 +346,6 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     w.plan = reinterpret_cast<uint32_t *>(ws + L.plan);
     w.lists = reinterpret_cast<uint32_t *>(ws + L.lists);
     w.list_stride = L.list_stride;
-    w.slot_first = reinterpret_cast<uint32_t *>(ws + L.slot_first);
-    w.slot_ntiles = reinterpret_cast<uint32_t *>(ws + L.slot_ntiles);
     w.tiles = reinterpret_cast<TileDesc *>(ws + L.tiles);
     w.tile_hist = reinterpret_cast<uint32_t *>(ws + L.tile_hist);
     w.seg_excl = reinterpret_cast<uint32_t *>(ws + L.seg_excl);
@@ -368,6 +403,7 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     hipLaunchKernelGGL((k_seg_tile_hist<K>), dim3(L.tile_cap), dim3(SEG_HIST_THREADS), 0, s,
                        static_cast<const K *>(c.keys_in), w);
     if (tm) tm->mark(INTSORT_KERNEL_DIGIT_HISTOGRAM, 0, s);
+    hipLaunchKernelGGL((k_seg_slot_sum<K>), dim3((L.tile_cap + SUM_TILES - 1) / SUM_TILES), dim3(256), 0, s, w);
     hipLaunchKernelGGL((k_seg_scan<K>), dim3(L.slot_cap), dim3(256), 0, s, w);
     if (tm) tm->mark(INTSORT_KERNEL_PLAN, 1, s);
 

@@ -14,8 +14,7 @@ constexpr uint32_t MAX_BUCKETS = 1u << 30;
 constexpr uint64_t MAX_SEGMENTS = 1ull << 24;
 
 struct SegLayout {
-    size_t counters, plan, lists, slot_first, slot_ntiles, tiles, bufs, tile_hist, seg_excl, slot_mask, status0,
-        status1;
+    size_t counters, plan, lists, tiles, bufs, tile_hist, seg_excl, slot_mask, status0, status1;
     size_t tmp_keys, tmp_vals, total;
     uint32_t slot_cap, tile_cap, list_stride, lds_cutoff;
 };
