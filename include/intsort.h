@@ -291,6 +291,31 @@ intsort_status intsort_bucket_histogram(intsort_ctx *ctx, intsort_key_type kt, c
                                         uint32_t *counts, void *stream);
 
 /*
+ * Graph capture: one HIP graph launch replays a whole sequence of sort calls.
+ *
+ * intsort_capture_begin starts recording `stream` (not the null stream) in
+ * thread-local capture mode; every sort call the caller then makes on that
+ * stream is recorded, not run: every one of them only enqueues kernels (no
+ * allocation, no synchronisation, no memset nodes), so each can be captured.
+ * intsort_capture_end stops recording and instantiates the graph in *graph.
+ * intsort_graph_launch enqueues one replay on `stream`: the same kernels on
+ * the same buffers, sizes and options, reading whatever the input buffers
+ * hold by then.  Each replay starts from the state its own first kernels
+ * set up (counters, look-back words), so replays may follow each other and
+ * other work freely.  The caller keeps every buffer the recorded calls name
+ * (inputs, outputs, workspaces, device offsets) alive and unchanged in size
+ * until intsort_graph_destroy.  Replays of one graph, or of graphs that
+ * share a workspace, must not overlap (same rule as the calls themselves).
+ * Timing must be off while recording (INTSORT_ERR_UNSUPPORTED otherwise).
+ */
+typedef struct intsort_graph intsort_graph;
+
+intsort_status intsort_capture_begin(intsort_ctx *ctx, void *stream);
+intsort_status intsort_capture_end(intsort_ctx *ctx, void *stream, intsort_graph **graph);
+intsort_status intsort_graph_launch(intsort_graph *graph, void *stream);
+intsort_status intsort_graph_destroy(intsort_graph *graph);
+
+/*
  * Per-kernel timing, for profiling.  intsort_timing_enable(ctx, 1) creates the
  * HIP events the context needs (host-side objects, no device memory); while
  * it is on, every sort call on the context records an event on its stream

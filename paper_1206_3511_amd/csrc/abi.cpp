@@ -18,6 +18,12 @@ struct intsort_ctx {
 
 int intsort::ctx_device(const intsort_ctx *ctx) { return ctx ? ctx->device : -1; }
 
+struct intsort_graph {
+    int device;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 namespace {
 
 using namespace intsort;
@@ -526,6 +532,68 @@ intsort_status intsort_read_device_error(intsort_ctx *ctx, const void *workspace
     } catch (...) {
         return INTSORT_ERR_INTERNAL;
     }
+}
+
+intsort_status intsort_capture_begin(intsort_ctx *ctx, void *stream)
+{
+    try {
+        if (!ctx || !stream) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (ctx->timer) return INTSORT_ERR_UNSUPPORTED;   // event records would be captured
+        intsort_status st = set_device(ctx);
+        if (st != INTSORT_OK) return st;
+        return from_hip(hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal));
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_capture_end(intsort_ctx *ctx, void *stream, intsort_graph **graph)
+{
+    try {
+        if (!ctx || !stream || !graph) return INTSORT_ERR_INVALID_ARGUMENT;
+        *graph = nullptr;
+        intsort_status st = set_device(ctx);
+        if (st != INTSORT_OK) return st;
+        hipGraph_t g = nullptr;
+        // ending the capture also ends it after a failed call in between
+        if (hipStreamEndCapture(static_cast<hipStream_t>(stream), &g) != hipSuccess || !g) return INTSORT_ERR_HIP;
+        intsort_graph *h = new (std::nothrow) intsort_graph;
+        if (!h) {
+            (void)hipGraphDestroy(g);
+            return INTSORT_ERR_INTERNAL;
+        }
+        h->device = ctx->device;
+        h->graph = g;
+        if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            delete h;
+            return INTSORT_ERR_HIP;
+        }
+        *graph = h;
+        return INTSORT_OK;
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_graph_launch(intsort_graph *graph, void *stream)
+{
+    try {
+        if (!graph || !graph->exec) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (hipSetDevice(graph->device) != hipSuccess) return INTSORT_ERR_HIP;
+        return from_hip(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_graph_destroy(intsort_graph *graph)
+{
+    if (!graph) return INTSORT_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    return INTSORT_OK;
 }
 
 }  // extern "C"

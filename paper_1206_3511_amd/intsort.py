@@ -38,6 +38,7 @@ EXPORTED = (
     "intsort_timing_enable", "intsort_timing_read", "intsort_batched_sort_keys",
     "intsort_server_create", "intsort_server_submit", "intsort_server_poll", "intsort_server_completed",
     "intsort_server_drain", "intsort_server_destroy",
+    "intsort_capture_begin", "intsort_capture_end", "intsort_graph_launch", "intsort_graph_destroy",
 )
 
 KERNEL_KINDS = ("init", "digit_histogram", "pass", "copy", "minmax", "bucket_histogram",
@@ -105,6 +106,10 @@ def lib():
                                                 ctypes.POINTER(ctypes.c_uint32), _vp]
         L.intsort_batched_sort_keys.argtypes = [_vp, _i, _vp, _u64, _u64, ctypes.POINTER(Options), _vp,
                                                 ctypes.c_size_t, _vp]
+        L.intsort_capture_begin.argtypes = [_vp, _vp]
+        L.intsort_capture_end.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
+        L.intsort_graph_launch.argtypes = [_vp, _vp]
+        L.intsort_graph_destroy.argtypes = [_vp]
         L.intsort_server_create.argtypes = [_vp, _u64, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_vp)]
         L.intsort_server_submit.argtypes = [_vp, _i, _vp, _vp, _u64, ctypes.POINTER(_u64)]
         L.intsort_server_poll.argtypes = [_vp, _u64, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]
@@ -361,6 +366,56 @@ def device_error(device: int = 0, stream=None) -> int:
     _check(lib().intsort_read_device_error(ctx.handle, ctx._ws.data_ptr(), ctx._ws.numel(), ctypes.byref(w),
                                            _stream_ptr(stream)), "intsort_read_device_error")
     return w.value
+
+
+class Graph:
+    """A recorded sequence of sort calls; launch() replays it on a stream."""
+
+    def __init__(self, handle, device: int, keep=()):
+        self.handle = handle
+        self.device = device
+        # the workspace the recorded calls use stays allocated while the
+        # graph exists, even if the context later takes a larger one
+        self._keep = list(keep)
+
+    def launch(self, stream=None):
+        _check(lib().intsort_graph_launch(self.handle, _stream_ptr(stream)), "intsort_graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().intsort_graph_destroy(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture(fn, stream, device: int = 0) -> Graph:
+    """Records the sort calls `fn()` makes on `stream` (a non-default
+    torch.cuda.Stream) into one HIP graph.  fn runs once eagerly first, so
+    that every workspace it needs exists before the recording (nothing may be
+    allocated while recording); it must pass its output tensors and device
+    offsets in, and use only this module's sort calls on `stream`."""
+    if stream is None or not stream.cuda_stream:
+        raise ValueError("capture needs a non-default stream")
+    with torch.cuda.stream(stream):
+        fn()
+    stream.synchronize()
+    ctx = context(device)
+    _check(lib().intsort_capture_begin(ctx.handle, stream.cuda_stream), "intsort_capture_begin")
+    g = _vp()
+    try:
+        with torch.cuda.stream(stream):
+            fn()
+    except BaseException:
+        if lib().intsort_capture_end(ctx.handle, stream.cuda_stream, ctypes.byref(g)) == OK:
+            lib().intsort_graph_destroy(g)
+        raise
+    _check(lib().intsort_capture_end(ctx.handle, stream.cuda_stream, ctypes.byref(g)), "intsort_capture_end")
+    return Graph(g, device, keep=[ctx._ws])
 
 
 class Server:

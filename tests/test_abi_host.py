@@ -164,3 +164,16 @@ def test_msd_is_bucket_sort_over_the_full_range(plan_ctx):
     bad = I.make_options()
     bad.algo = 3
     assert _call_sort(plan_ctx, opts=bad) == I.ERR_INVALID_ARGUMENT
+
+
+def test_graph_capture_argument_checks(plan_ctx):
+    L = I.lib()
+    g = ctypes.c_void_p()
+    assert L.intsort_capture_begin(plan_ctx.handle, None) == I.ERR_INVALID_ARGUMENT
+    assert L.intsort_capture_begin(None, 0x1000) == I.ERR_INVALID_ARGUMENT
+    # a planning context has no device to record on
+    assert L.intsort_capture_begin(plan_ctx.handle, 0x1000) == I.ERR_UNSUPPORTED
+    assert L.intsort_capture_end(plan_ctx.handle, None, ctypes.byref(g)) == I.ERR_INVALID_ARGUMENT
+    assert L.intsort_capture_end(plan_ctx.handle, 0x1000, None) == I.ERR_INVALID_ARGUMENT
+    assert L.intsort_graph_launch(None, None) == I.ERR_INVALID_ARGUMENT
+    assert L.intsort_graph_destroy(None) == I.OK
