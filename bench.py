@@ -579,7 +579,7 @@ def main():
                     help="keys of the same input that the CPU oracle sorts (0 = all of them)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the CPU oracle sort until this much time has passed")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving trace")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the serving trace")
     ap.add_argument("--serve-out-gb", type=float, default=64.0,
                     help="serving trace: output memory the requests in flight may hold")
     ap.add_argument("--calibrate-copy", action="store_true",
