@@ -102,20 +102,19 @@ __device__ __forceinline__ uint32_t block_scan_1b(uint32_t v, uint32_t *s_tmp)
     return below + incl - v;
 }
 
-// Adds one to bin d of an LDS histogram; a wave whose active lanes all hold
-// the same bin adds once instead of colliding on one word.  (Lanes that hit
-// one word in one atomic instruction are served one after another.  Catching
-// waves where only most lanes agree costs the common case of keys spread over
-// many bins a third more time, so only the uniform wave is caught.)
+// Adds one to bin d of an LDS histogram.  Lanes that hit one word in one
+// atomic instruction are served one after another, so the lanes that share
+// the first active lane's bin add as one group: that lane adds the group's
+// size, and every lane with another bin adds one, all in one instruction.  A
+// wave of sorted or nearly sorted keys then costs one or a few adds instead
+// of up to 64 on one word; keys spread over many bins pay one compare more.
 __device__ __forceinline__ void lds_count(uint32_t *s_h, uint32_t d)
 {
+    const uint32_t lane = lane_id();
+    const bool lead = lane == first_lane_value(lane);   // the lane d0 comes from
     const uint32_t d0 = first_lane_value(d);
-    const uint64_t act = ballot(true);
-    if (ballot(d != d0) == 0) {
-        if (mbcnt(act) == 0) atomicAdd(&s_h[d0], popc64(act));
-    } else {
-        atomicAdd(&s_h[d], 1u);
-    }
+    const uint64_t same = ballot(d == d0);
+    if (d != d0 || lead) atomicAdd(&s_h[d], lead ? popc64(same) : 1u);
 }
 
 }  // namespace intsort
