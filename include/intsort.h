@@ -167,8 +167,9 @@ intsort_status intsort_workspace_size(const intsort_ctx *ctx, intsort_key_type k
 
 /*
  * Sorts n keys (section 2): keys_out receives the nondecreasing permutation
- * of keys_in.  opts->algo picks radix (section 2.5) or bucket (section 2.3)
- * sort; both give identical bytes.  n == 0 is a no-op.
+ * of keys_in (in the order of intsort_key_type for signed and floating-point
+ * keys).  opts->algo picks LSD radix (section 2.5), bucket (section 2.3) or
+ * MSD-first radix sort; all give identical bytes.  n == 0 is a no-op.
  */
 intsort_status intsort_sort_keys(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in,
                                  void *keys_out, uint64_t n, const intsort_options *opts,
