@@ -19,6 +19,13 @@ def main():
         k, _ = w.config3_pairs(v, 1 << 16)
         out["config3"][v] = hex(w.checksum(k))
     out["paper_cases"] = {str(c): hex(w.checksum(w.paper_case(c, 1 << 16)[0])) for c in range(1, 7)}
+    out["signed_ieee"] = {
+        "int32": hex(w.checksum(w.signed_keys(1 << 16, 32, seed=1))),
+        "int64": hex(w.checksum(w.signed_keys(1 << 16, 64, seed=1))),
+        "int32_b12": hex(w.checksum(w.signed_keys(1 << 16, 32, seed=1, spread_bits=12))),
+        "float32": hex(w.checksum(w.ieee_keys(1 << 16, 32, seed=1))),
+        "float64": hex(w.checksum(w.ieee_keys(1 << 16, 64, seed=1))),
+    }
     sizes, dists = w.segment_plan(64)
     out["segment_plan_64"] = {"sizes": [int(x) for x in sizes], "dists": [int(x) for x in dists]}
     with open(os.path.join(HERE, "input_checksums.json"), "w") as f:

@@ -87,3 +87,29 @@ def test_paper_cases_shapes_and_checksums():
     assert np.unique(others).size == others.size   # distinct when they fit
     big, _ = w.paper_case(6, 3 * 10**6)            # 2*10^6 others cannot be distinct in [0, 10^6]
     assert int((big == 500_000).sum()) == 10**6
+
+
+def test_signed_and_ieee_generators():
+    """Recorded checksums, value classes and the repeats the tests rely on."""
+    gold = json.load(open(os.path.join(HERE, "golden", "input_checksums.json")))["signed_ieee"]
+    n = 1 << 16
+    assert hex(w.checksum(w.signed_keys(n, 32, seed=1))) == gold["int32"]
+    assert hex(w.checksum(w.signed_keys(n, 64, seed=1))) == gold["int64"]
+    b = w.signed_keys(n, 32, seed=1, spread_bits=12)
+    assert hex(w.checksum(b)) == gold["int32_b12"]
+    assert b.dtype == np.int32 and b.min() >= -(1 << 12) and b.max() < (1 << 12) and (b < 0).any()
+    for width, name in ((32, "float32"), (64, "float64")):
+        f = w.ieee_keys(n, width, seed=1)
+        assert hex(w.checksum(f)) == gold[name]
+        ut = np.uint32 if width == 32 else np.uint64
+        bits = f.view(ut)
+        sign = ut(1) << ut(width - 1)
+        # every special class occurs: +-0, +-inf, NaNs of both signs, subnormals
+        assert (bits == 0).any() and (bits == sign).any()
+        assert np.isposinf(f).any() and np.isneginf(f).any()
+        nan = np.isnan(f)
+        assert (nan & ((bits & sign) != 0)).any() and (nan & ((bits & sign) == 0)).any()
+        tiny = np.finfo(f.dtype).tiny
+        assert ((np.abs(f) < tiny) & (f != 0)).any()
+        # every ninth key repeats the key four places earlier
+        np.testing.assert_array_equal(bits[9::9], bits[5:-4:9][: bits[9::9].size])
