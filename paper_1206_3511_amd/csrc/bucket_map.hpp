@@ -25,6 +25,7 @@ struct BucketMap {
     uint64_t mul;         // floor(2^64 B / R) + 1 when fast32
     bool full64;          // R == 2^64
     bool fast32;          // R <= 2^32 and B < R: 32-bit keys use mul
+    bool fast64;          // R <= 2^62: 64-bit keys need one correction only
 };
 
 __device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, uint32_t B)
@@ -39,6 +40,7 @@ __device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, u
     m.scale = (double)B / R;
     m.inv = m.full64 ? 1ull : ~0ull / (m.range_m1 + 1);
     m.fast32 = !m.full64 && m.range_m1 <= 0xffffffffull && (uint64_t)B <= m.range_m1;
+    m.fast64 = !m.full64 && m.range_m1 < (1ull << 62);
     m.mul = 0;
     if (m.fast32) {
         // 2^64 = q R + r with 0 <= r < R, from floor((2^64 - 1) / R)
@@ -90,6 +92,19 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint64_t k)
     const uint64_t B = m.buckets;
     if (m.full64) return (uint32_t)__umul64hi(x, B);   // x * B / 2^64
     const uint64_t R = m.range_m1 + 1;
+    if (m.fast64) {
+        // keys above the range (a declared bound) take the last bucket
+        if (x >= R) return (uint32_t)(B - 1);
+        // The double estimate is within one of b(k): its relative error is
+        // a few 2^-53 and b(k) < 2^30.  The remainder x B - q R then lies in
+        // (-R, 2R), which for R <= 2^62 is exact in wrapping 64-bit
+        // arithmetic read as signed, so one correction makes q exact.
+        int64_t q = (int64_t)((double)x * m.scale);
+        const int64_t r = (int64_t)(x * B - (uint64_t)q * R);
+        if (r < 0) q--;
+        else if (r >= (int64_t)R) q++;
+        return (uint32_t)(q < 0 ? 0 : (q < (int64_t)B ? q : (int64_t)B - 1));
+    }
     // P = x * B as (phi, plo)
     const uint64_t plo = x * B, phi = __umul64hi(x, B);
     uint64_t q = (uint64_t)((double)x * m.scale);
