@@ -96,6 +96,18 @@ typedef enum intsort_algo {
 /* option flags */
 #define INTSORT_FLAG_NO_PASS_SKIP 0x1u /* radix: run every digit pass even when
                                           a digit is the same for all keys */
+#define INTSORT_FLAG_CHECK_SEGMENTS 0x2u /* segmented and batched: first check
+                                            on the device the layout the caller
+                                            gave (offsets nondecreasing from 0 to
+                                            n_total; every array at most
+                                            total_keys long, with non-null,
+                                            16-byte aligned buffers when not
+                                            empty, and all of them together
+                                            at most total_keys long); if a
+                                            check fails, set
+                                            INTSORT_DEVERR_BAD_SEGMENTS in the
+                                            device error word and sort nothing
+                                            (outputs unspecified) */
 
 /*
  * Options.  A zero field means "library default".
@@ -352,10 +364,13 @@ intsort_status intsort_timing_read(intsort_ctx *ctx, intsort_kernel_time *out, u
 
 /*
  * Device-side error word of the last sort that used `workspace`: 0 when no
- * kernel reported a problem.  A nonzero value means a bounded wait inside a
- * kernel gave up (the result is then not valid).  Reads device memory, so
- * it synchronises `stream`.
+ * kernel reported a problem; otherwise an OR of the bits below, and the
+ * result is not valid.  Reads device memory, so it synchronises `stream`.
  */
+#define INTSORT_DEVERR_LOOKBACK_TIMEOUT 0x1u /* a bounded wait inside a kernel gave up */
+#define INTSORT_DEVERR_BAD_TILE 0x2u         /* a tile id or look-back walk left its range */
+#define INTSORT_DEVERR_SCATTER_RANGE 0x4u    /* a computed destination fell outside [0, n) */
+#define INTSORT_DEVERR_BAD_SEGMENTS 0x8u     /* INTSORT_FLAG_CHECK_SEGMENTS found a bad segment */
 intsort_status intsort_read_device_error(intsort_ctx *ctx, const void *workspace,
                                          size_t workspace_bytes, uint32_t *error_word,
                                          void *stream);

@@ -18,6 +18,11 @@ struct intsort_ctx {
 
 int intsort::ctx_device(const intsort_ctx *ctx) { return ctx ? ctx->device : -1; }
 
+static_assert(INTSORT_DEVERR_LOOKBACK_TIMEOUT == intsort::DEVERR_LOOKBACK_TIMEOUT &&
+                  INTSORT_DEVERR_BAD_TILE == intsort::DEVERR_BAD_TILE &&
+                  INTSORT_DEVERR_SCATTER_RANGE == intsort::DEVERR_SCATTER_RANGE,
+              "public error bits match the kernels'");
+
 struct intsort_graph {
     int device;
     hipGraph_t graph = nullptr;
@@ -70,7 +75,7 @@ intsort_status read_opts(const intsort_options *in, intsort_key_type kt, intsort
     if (!unsigned_kt(kt) && (out->algo != INTSORT_RADIX_LSD || out->digit_bits != 8)) return INTSORT_ERR_UNSUPPORTED;
     if (out->num_buckets == 0) out->num_buckets = kt == INTSORT_U64 ? 65536u : 1024u;
     if (out->num_buckets > MAX_BUCKETS) return INTSORT_ERR_UNSUPPORTED;
-    if (out->flags & ~INTSORT_FLAG_NO_PASS_SKIP) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (out->flags & ~(INTSORT_FLAG_NO_PASS_SKIP | INTSORT_FLAG_CHECK_SEGMENTS)) return INTSORT_ERR_INVALID_ARGUMENT;
     // a declared bound beyond the key width says nothing a measured range
     // would not, and 32-bit keys compute their bucket with 32-bit ranges
     if (kt == INTSORT_U32 && out->key_bound > 0xffffffffull) return INTSORT_ERR_INVALID_ARGUMENT;

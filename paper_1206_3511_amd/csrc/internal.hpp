@@ -35,6 +35,7 @@ constexpr int CTR_SEG_CLASS = 32;   // [4] segments per on-chip size class
 constexpr int CTR_SEG_SLOTS = 36;   // large segments
 constexpr int CTR_SEG_TILES = 37;   // tiles of the large segments
 constexpr int CTR_SEG_TMP = 38;     // scratch keys handed out to large separate arrays
+constexpr int CTR_SEG_SUM = 40;     // [2] 64-bit sum of the segment lengths (the layout check)
 constexpr int CTR_WORDS = 64;
 
 // HIP events around kernels (profiling only).  Events accumulate over calls

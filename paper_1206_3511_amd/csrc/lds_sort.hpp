@@ -48,6 +48,14 @@ struct PackedSrc {
         vi = vin ? vin + lo : nullptr;
         vo = vout ? vout + lo : nullptr;
     }
+    // segment s keeps inside [0, n): offsets nondecreasing from 0 to n;
+    // len is its length when it is valid
+    __device__ bool valid(uint64_t s, uint64_t segments, uint64_t n, uint64_t &len) const
+    {
+        const uint64_t lo = offsets[s], hi = offsets[s + 1];
+        len = hi > lo ? hi - lo : 0;
+        return lo <= hi && hi <= n && (s != 0 || lo == 0) && (s + 1 != segments || hi == n);
+    }
 };
 
 // ... or separate arrays, one descriptor each (keys only)
@@ -64,6 +72,16 @@ struct DescSrc {
         kout = static_cast<K *>(e.keys_out);
         vi = nullptr;
         vo = nullptr;
+    }
+    // one array: at most n keys (the batch total), and 16-byte aligned,
+    // non-null buffers when it is not empty; len is its length
+    __device__ bool valid(uint64_t s, uint64_t, uint64_t n, uint64_t &len) const
+    {
+        const intsort_segment_desc e = d[s];
+        len = e.n;
+        if (e.n == 0) return true;
+        const uintptr_t a = reinterpret_cast<uintptr_t>(e.keys_in), b = reinterpret_cast<uintptr_t>(e.keys_out);
+        return e.n <= n && a != 0 && b != 0 && (a & 15u) == 0 && (b & 15u) == 0;
     }
 };
 

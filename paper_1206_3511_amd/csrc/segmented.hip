@@ -52,7 +52,30 @@ struct SegWs {
     uint32_t *slot_mask;      // [slot_cap] digit passes each large segment runs
     uint32_t skip;            // leave out passes whose digit is constant in the segment
     uint32_t min_size;        // segments of at most this many keys are left alone
+    uint32_t check;           // k_seg_check ran: sort nothing if it found a bad segment
+    uint64_t n_total;         // keys of the whole call (the bound of the length sum)
 };
+
+// error-word bit: a segment (or array) the caller described would reach
+// outside its buffers; with INTSORT_FLAG_CHECK_SEGMENTS nothing is sorted
+constexpr uint32_t DEVERR_BAD_SEGMENTS = 8u;
+static_assert(DEVERR_BAD_SEGMENTS == INTSORT_DEVERR_BAD_SEGMENTS, "public error bit matches");
+
+// One thread per segment: the caller's segment layout, checked before any
+// kernel uses it (INTSORT_FLAG_CHECK_SEGMENTS).  Each segment must be valid
+// on its own, and the lengths together at most n: k_seg_classify compares
+// the sum collected here.
+template <class Src>
+__global__ __launch_bounds__(256) void k_seg_check(Src src, uint64_t num_segments, uint64_t n, uint32_t *counters)
+{
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t len = 0;
+    if (s < num_segments && !src.valid(s, num_segments, n, len)) atomicOr(&counters[CTR_ERROR], DEVERR_BAD_SEGMENTS);
+    // lengths are below 2^32 and segments at most 2^32: no overflow
+    for (int o = WAVE / 2; o > 0; o /= 2) len += __shfl_xor(len, o, WAVE);
+    if (lane_id() == 0 && len)
+        atomicAdd(reinterpret_cast<unsigned long long *>(counters + CTR_SEG_SUM), (unsigned long long)len);
+}
 
 // One thread per segment: classify by size; a large segment reserves a run
 // of consecutive tile ids and writes their descriptors (and, for separate
@@ -74,6 +97,14 @@ __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segm
             pw[0] = 1; pw[1] = prev; pw[2] = dst; pw[3] = q;
             prev = dst;
         }
+    }
+    // a bad layout found by k_seg_check: no segment is listed, so every
+    // later kernel finds nothing to do
+    if (w.check) {
+        const uint64_t sum = *reinterpret_cast<const uint64_t *>(w.counters + CTR_SEG_SUM);
+        const bool bad_sum = sum > w.n_total;
+        if (bad_sum && s == 0) atomicOr(&w.counters[CTR_ERROR], DEVERR_BAD_SEGMENTS);
+        if (bad_sum || (w.counters[CTR_ERROR] & DEVERR_BAD_SEGMENTS)) return;
     }
     const K *kin = nullptr;
     K *kout = nullptr;
@@ -359,10 +390,14 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     w.slot_mask = reinterpret_cast<uint32_t *>(ws + L.slot_mask);
     w.skip = (c.opts.flags & INTSORT_FLAG_NO_PASS_SKIP) ? 0u : 1u;
     w.min_size = c.min_size;
+    w.check = (c.opts.flags & INTSORT_FLAG_CHECK_SEGMENTS) ? 1u : 0u;
+    w.n_total = c.n;
 
     if (tm) tm->start(s);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, w.counters, (uint64_t)CTR_WORDS, 0u);
     const uint32_t cgrid = (uint32_t)((c.num_segments + 255) / 256);
+    if (w.check)
+        hipLaunchKernelGGL((k_seg_check<Src>), dim3(cgrid), dim3(256), 0, s, src, c.num_segments, c.n, w.counters);
     hipLaunchKernelGGL((k_seg_classify<K, Src>), dim3(cgrid), dim3(256), 0, s, src, c.num_segments, w,
                        (uint32_t)PASSES);
     if (tm) tm->mark(INTSORT_KERNEL_PLAN, 0, s);

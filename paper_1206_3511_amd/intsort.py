@@ -29,6 +29,8 @@ ERR_NOT_READY = 8
 U32, U64, I32, I64, F32, F64 = 0, 1, 2, 3, 4, 5
 RADIX, BUCKET, MSD = 0, 1, 2
 FLAG_NO_PASS_SKIP = 0x1
+FLAG_CHECK_SEGMENTS = 0x2
+DEVERR_BAD_SEGMENTS = 0x8
 
 EXPORTED = (
     "intsort_status_string", "intsort_default_options", "intsort_create", "intsort_destroy",
@@ -138,7 +140,7 @@ def _check(rc: int, where: str):
 
 def make_options(algo: str | int = "radix", digit_bits: int = 0, num_buckets: int = 0,
                  lds_cutoff: int = 0, max_passes: int = 0, skip_passes: bool = True,
-                 key_bound: int = 0) -> Options:
+                 key_bound: int = 0, check_segments: bool = False) -> Options:
     o = Options()
     lib().intsort_default_options(ctypes.byref(o))
     o.algo = algo if isinstance(algo, int) else {"radix": RADIX, "bucket": BUCKET, "msd": MSD}[algo]
@@ -146,7 +148,7 @@ def make_options(algo: str | int = "radix", digit_bits: int = 0, num_buckets: in
     o.num_buckets = num_buckets
     o.lds_cutoff = lds_cutoff
     o.max_passes = max_passes
-    o.flags = 0 if skip_passes else FLAG_NO_PASS_SKIP
+    o.flags = (0 if skip_passes else FLAG_NO_PASS_SKIP) | (FLAG_CHECK_SEGMENTS if check_segments else 0)
     o.key_bound = key_bound
     return o
 

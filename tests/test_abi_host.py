@@ -177,3 +177,15 @@ def test_graph_capture_argument_checks(plan_ctx):
     assert L.intsort_capture_end(plan_ctx.handle, 0x1000, None) == I.ERR_INVALID_ARGUMENT
     assert L.intsort_graph_launch(None, None) == I.ERR_INVALID_ARGUMENT
     assert L.intsort_graph_destroy(None) == I.OK
+
+
+def test_check_segments_flag_accepted(plan_ctx):
+    b = ctypes.c_size_t(0)
+    o = I.make_options(check_segments=True)
+    assert o.flags == I.FLAG_CHECK_SEGMENTS
+    assert I.lib().intsort_workspace_size(plan_ctx.handle, I.U32, 0, 1000, 10, ctypes.byref(o),
+                                          ctypes.byref(b)) == I.OK
+    bad = I.make_options()
+    bad.flags = 0x4
+    assert I.lib().intsort_workspace_size(plan_ctx.handle, I.U32, 0, 1000, 10, ctypes.byref(bad),
+                                          ctypes.byref(b)) == I.ERR_INVALID_ARGUMENT

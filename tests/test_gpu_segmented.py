@@ -116,3 +116,56 @@ def test_config4_full_batch():
         a, b = int(offsets[s]), int(offsets[s + 1])
         np.testing.assert_array_equal(out[a:b], oracle.radix_lsd(keys[a:b]).keys)
     assert I.device_error(0) == 0
+
+
+def test_check_segments_flag():
+    """With INTSORT_FLAG_CHECK_SEGMENTS the segment layout is checked on the
+    device first: a valid one sorts as usual with a clean error word; a bad
+    one (decreasing offsets, an end past the keys, a start other than 0) sets
+    the bad-segments bit and nothing is sorted.  A valid call afterwards is
+    correct again."""
+    n = 50_000
+    keys = rand_keys(np.random.default_rng(12), n, np.uint32)
+    good = np.array([0, 100, 20_000, n], dtype=np.uint64)
+    out, _ = _run(keys, good, check_segments=True)
+    np.testing.assert_array_equal(out, oracle.segmented(keys, good)[0])
+    assert I.device_error(0) == 0
+    for bad in ([0, 30_000, 20_000, n], [0, 100, n + 10_000], [5, 100, n]):
+        print(f"bad layout {bad}", flush=True)
+        _run(keys, np.array(bad, dtype=np.uint64), check_segments=True)
+        assert I.device_error(0) & I.DEVERR_BAD_SEGMENTS
+    out, _ = _run(keys, good, check_segments=True)
+    np.testing.assert_array_equal(out, oracle.segmented(keys, good)[0])
+    assert I.device_error(0) == 0
+
+
+def test_check_segments_flag_batched():
+    """The same check for separate arrays: a descriptor whose buffer is not
+    16-byte aligned, or lengths that add up past total_keys, are reported and
+    nothing is sorted; a good batch afterwards sorts."""
+    import ctypes
+    a = dev(rand_keys(np.random.default_rng(13), 4096, np.uint32))
+    b = torch.empty_like(a)
+    ctx = I.context(0)
+    o = I.make_options(check_segments=True)
+    p, q = a.data_ptr(), b.data_ptr()
+    cases = [([[p, q, 1000]], 4096, False),
+             ([[p + 4, q, 1000]], 4096, True),                      # misaligned input
+             ([[p, q, 1000], [p + 4096, q + 4096, 1000]], 1500, True),   # 2000 keys > total 1500
+             ([[p, q, 2000], [p + 8000, q + 8000, 2096]], 4096, False)]
+    for rows, total, expect_bad in cases:
+        print(f"batched check {rows} total={total}", flush=True)
+        desc = torch.tensor(rows, dtype=torch.int64).to("cuda:0")
+        ws = ctx.workspace(ctx.workspace_size(I.U32, False, total, len(rows), o))
+        rc = I.lib().intsort_batched_sort_keys(ctx.handle, I.U32, desc.data_ptr(), len(rows), total, ctypes.byref(o),
+                                               ws.data_ptr(), ws.numel(), None)
+        assert rc == I.OK
+        torch.cuda.synchronize()
+        assert bool(I.device_error(0) & I.DEVERR_BAD_SEGMENTS) == expect_bad
+        if not expect_bad:
+            ha, hb = host(a), host(b)
+            at = 0
+            for r in rows:
+                m = r[2]
+                np.testing.assert_array_equal(hb[at:at + m], np.sort(ha[at:at + m]))
+                at += m
