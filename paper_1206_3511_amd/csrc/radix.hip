@@ -84,7 +84,8 @@ struct HistArgs {
     uint32_t tiles_per_wg; // tiles per chunk (<= FIRST_PASS_TILES_PER_CHUNK): one workgroup each
 };
 
-template <typename K, int BITS, int ORDER>
+// PER_TILE: the first pass's digits are counted per tile (a.tile_counts set)
+template <typename K, int BITS, int ORDER, bool PER_TILE>
 __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__restrict__ keys, HistArgs a)
 {
     constexpr int RADIX = 1 << BITS;
@@ -94,14 +95,30 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
     struct alignas(16) Vec { K v[KPV]; };
 
     __shared__ uint32_t s_h[PASSES * RADIX];
-    constexpr bool TILED = RADIX <= HIST_THREADS;   // tile counts: one thread per digit
+    constexpr bool TILED = PER_TILE && RADIX <= HIST_THREADS;   // tile counts: one thread per digit
     // first-pass digits of each tile of the workgroup's chunk
     __shared__ uint32_t s_t[TILED ? FIRST_PASS_TILES_PER_CHUNK * RADIX : 1];
+    // With 32-bit keys the chunk's other digits go to HC copies of their
+    // counts, lane l adding into copy l % HC, two 16-bit counts to a word:
+    // word (p - 1, v / 2, copy) holds digit value v of pass p in half v % 2.
+    // Lanes of one instruction then reach at most two words per bank and at
+    // most two share a word, whatever the digits; a single shared copy
+    // serialises the lanes that meet on a bank or an address.
+    constexpr bool COPIES = TILED && sizeof(K) == 4;
+    constexpr int HC = 16;
+    constexpr int HALF = RADIX / 2;
+    static_assert(!COPIES || HIST_THREADS % HC == 0, "every copy has the same threads");
+    // one copy counts at most HIST_THREADS / HC threads' keys of one chunk
+    static_assert(!COPIES || (uint64_t)FIRST_PASS_TILES_PER_CHUNK * PassCfg<K, BITS>::TILE / HC < 65536u,
+                  "16-bit counts cannot overflow");
+    __shared__ uint32_t s_c[COPIES ? (PASSES - 1) * HALF * HC : 1];
 
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < (uint32_t)(PASSES * RADIX); i += HIST_THREADS) s_h[i] = 0;
     if (TILED)
         for (uint32_t i = tid; i < (uint32_t)(FIRST_PASS_TILES_PER_CHUNK * RADIX); i += HIST_THREADS) s_t[i] = 0;
+    if (COPIES)
+        for (uint32_t i = tid; i < (uint32_t)((PASSES - 1) * HALF * HC); i += HIST_THREADS) s_c[i] = 0;
     {
         const uint64_t stride = (uint64_t)gridDim.x * HIST_THREADS;
         for (uint64_t i = (uint64_t)blockIdx.x * HIST_THREADS + tid; i < a.status0_words; i += stride)
@@ -112,7 +129,8 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
     const uint32_t n = a.n;
     if constexpr (TILED) if (a.tile_counts) {
         // one chunk of consecutive first-pass tiles: digit 0 of every key
-        // goes to its tile's row of s_t, the other digits to s_h as below
+        // goes to its tile's row of s_t, the other digits count for the
+        // whole chunk
         constexpr uint32_t TILE = PassCfg<K, BITS>::TILE;
         constexpr uint32_t VPT = TILE / KPV;   // vectors per tile
         const uint32_t t0 = blockIdx.x * a.tiles_per_wg;
@@ -121,11 +139,18 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
         const uint32_t cnt = min(n, t1 * TILE) - k0;
         const uint32_t nv = cnt / KPV;
         const Vec *tv = reinterpret_cast<const Vec *>(keys + k0);
+        uint32_t *my_c = s_c + tid % HC;
         auto count_key = [&](K key, uint32_t slot) {
             const K k = KeyOrder<ORDER>::ordered(key);
             lds_count(s_t + slot * RADIX, digit_at<K>(k, 0u, MASK));
 #pragma unroll
-            for (int p = 1; p < PASSES; p++) lds_count(s_h + p * RADIX, digit_at<K>(k, (uint32_t)(p * BITS), MASK));
+            for (int p = 1; p < PASSES; p++) {
+                const uint32_t d = digit_at<K>(k, (uint32_t)(p * BITS), MASK);
+                if constexpr (COPIES)
+                    atomicAdd(my_c + ((p - 1) * HALF + (d >> 1)) * HC, 1u << (16 * (d & 1)));
+                else
+                    lds_count(s_h + p * RADIX, d);
+            }
         };
         for (uint32_t v0 = tid; v0 < nv; v0 += HIST_THREADS * HIST_UNROLL) {
             Vec x[HIST_UNROLL];
@@ -153,6 +178,18 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
             // digit 0 is counted only in s_t, so its words of s_h are this
             // thread's alone
             s_h[tid] += acc;
+        }
+        if constexpr (COPIES) {
+            // the other passes' counts: the sum of the copies (read from a
+            // rotated start, so that the threads spread over the banks)
+            for (uint32_t i = tid; i < (uint32_t)((PASSES - 1) * RADIX); i += HIST_THREADS) {
+                const uint32_t p1 = i / RADIX, v = i % RADIX;
+                const uint32_t *w = s_c + (p1 * HALF + (v >> 1)) * HC;
+                uint32_t sum = 0;
+#pragma unroll
+                for (int c = 0; c < HC; c++) sum += (w[(c + (v >> 1)) % HC] >> (16 * (v & 1))) & 0xffffu;
+                s_h[(p1 + 1) * RADIX + v] = sum;
+            }
         }
         __syncthreads();
         uint32_t *hdst = a.hist + (blockIdx.x % a.copies) * (uint32_t)(PASSES * RADIX);
@@ -465,8 +502,17 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
         h.tiles_per_wg = first_pass_tiles_per_chunk(L.num_tiles);
         blocks = first_pass_chunks(L.num_tiles);
     }
-    hipLaunchKernelGGL((k_digit_histogram<K, BITS, ORDER>), dim3((uint32_t)blocks), dim3(HIST_THREADS), 0, s,
-                       static_cast<const K *>(c.keys_in), h);
+    bool launched = false;
+    if constexpr (sizeof(K) == 4 && C::RADIX <= HIST_THREADS) {
+        if (h.tile_counts) {
+            hipLaunchKernelGGL((k_digit_histogram<K, BITS, ORDER, true>), dim3((uint32_t)blocks), dim3(HIST_THREADS),
+                               0, s, static_cast<const K *>(c.keys_in), h);
+            launched = true;
+        }
+    }
+    if (!launched)
+        hipLaunchKernelGGL((k_digit_histogram<K, BITS, ORDER, false>), dim3((uint32_t)blocks), dim3(HIST_THREADS), 0,
+                           s, static_cast<const K *>(c.keys_in), h);
     if (t) t->mark(INTSORT_KERNEL_DIGIT_HISTOGRAM, 0, s);
     if (finalize) {
         hipLaunchKernelGGL((k_digit_plan<K, BITS>), dim3(1), dim3(HIST_THREADS), 0, s, h);
