@@ -385,16 +385,16 @@ RadixGeom radix_geometry(int key_bytes, int bits)
 // consecutive tiles, one chunk per workgroup: about FIRST_PASS_CHUNKS chunks,
 // of at most FIRST_PASS_TILES_PER_CHUNK tiles
 constexpr uint64_t FIRST_PASS_CHUNKS = 1024;
-// ... for 32-bit keys without values and at least this many tiles: there the
-// first pass without look-back saves more than the scan over chunks costs
-// (measured: 100M keys, the pass 0.286 -> 0.239 ms for 0.020 ms more in the
-// histogram and the scan; with 64-bit keys and values the first pass got
-// slower)
+// ... for 32-bit keys (with or without values) and at least this many
+// tiles: there the first pass without look-back saves more than the scan
+// over chunks costs (measured on 100M keys: keys only, the pass 0.286 ->
+// 0.239 ms for 0.020 ms more in the histogram and the scan; with values
+// 0.427 -> 0.411 ms; with 64-bit keys and values the first pass got slower)
 constexpr uint64_t FIRST_PASS_MIN_TILES = 2048;
 
-static bool scanned_first_pass(int key_bytes, bool pairs, uint64_t tiles, bool chunked)
+static bool scanned_first_pass(int key_bytes, bool, uint64_t tiles, bool chunked)
 {
-    return !chunked && key_bytes == 4 && !pairs && tiles >= FIRST_PASS_MIN_TILES;
+    return !chunked && key_bytes == 4 && tiles >= FIRST_PASS_MIN_TILES;
 }
 
 static uint32_t first_pass_tiles_per_chunk(uint64_t tiles)
@@ -572,7 +572,7 @@ static hipError_t run_typed(const RadixCall &c, hipStream_t s)
             hipLaunchKernelGGL((k_chunk_sort<K, BITS, PAIRS, DG>), dim3(ca.chunks), dim3(H::NT), 0, s, a, ca, dg);
         } else {
             bool scanned = false;
-            if constexpr (!PAIRS && sizeof(K) == 4) {
+            if constexpr (sizeof(K) == 4) {
                 if (p == 0 && scanned_first_pass(c.key_bytes, c.pairs, L.num_tiles, false)) {
                     // the first pass's per-tile offsets are known: no look-back
                     const ScannedTiles tl{(uint32_t)c.n, (uint32_t)L.num_tiles,

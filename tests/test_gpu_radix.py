@@ -148,8 +148,8 @@ def test_config2_full_size(dist):
     assert I.device_error(0) == 0
 
 
-# 32-bit key sorts of at least 2048 tiles take the first pass without a
-# look-back: its per-tile digit offsets come from the histogram kernel and a
+# 32-bit key sorts (keys alone or with values) of at least 2048 tiles take
+# the first pass without a look-back: its per-tile digit offsets come from the histogram kernel and a
 # scan over chunks of tiles
 SCANNED_N = 2048 * 16384 + 4099
 
@@ -168,3 +168,19 @@ def test_scanned_first_pass(case):
     # the intermediate array after the first pass alone
     one = host(I.sort(dev(keys), max_passes=1))
     np.testing.assert_array_equal(one, oracle.radix_lsd(keys, r=8, want_passes=True).pass_keys[0])
+
+
+@pytest.mark.parametrize("case", ["uniform", "small_range"])
+def test_scanned_first_pass_pairs(case):
+    """Key-value sorts through the first pass without a look-back: keys and
+    stable values bit-exact against the oracle."""
+    print(f"scanned first pass pairs n={SCANNED_N} case={case}", flush=True)
+    keys = workloads.config2_keys(0, SCANNED_N, seed=22)
+    if case == "small_range":
+        keys = keys >> np.uint32(22)
+    vals = np.arange(SCANNED_N, dtype=np.uint32)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals))
+    ref = oracle.radix_lsd(keys, vals, r=8)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+    assert I.device_error(0) == 0
