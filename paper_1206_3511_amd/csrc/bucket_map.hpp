@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device_common.hpp"
+
 namespace intsort {
 
 struct BucketMap {
@@ -122,6 +124,23 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint64_t k)
         break;
     }
     return (uint32_t)(q < B ? q : B - 1);
+}
+
+// Whether vector v of an array (its KPV keys x) is in nondecreasing order,
+// inside and against the key before it.  The lanes of a wave hold
+// consecutive vectors, so a lane takes that key from the lane below and
+// lane 0 loads it.  Every lane whose vector is valid calls it together with
+// all lanes below it; lanes with v >= nvec get true.
+template <typename K, int KPV>
+__device__ __forceinline__ bool vector_in_order(const K *x, const K *keys, uint64_t v, uint64_t nvec)
+{
+    K prev = __shfl_up(x[KPV - 1], 1, WAVE);
+    if (lane_id() == 0 && v > 0 && v < nvec) prev = keys[v * KPV - 1];
+    if (v >= nvec) return true;
+    bool ok = v == 0 || x[0] >= prev;
+#pragma unroll
+    for (int e = 1; e < KPV; e++) ok = ok && x[e] >= x[e - 1];
+    return ok;
 }
 
 }  // namespace intsort

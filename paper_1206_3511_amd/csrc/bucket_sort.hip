@@ -3,7 +3,11 @@
 // Algorithm 2 drops every key, in input order, into the bucket its value
 // selects, sorts every bucket (insertion sort, Algorithm 1) and concatenates
 // the buckets.  On the GPU:
-//   1. min and max of the keys (the value range the paper assumes known);
+//   1. min and max of the keys (the value range the paper assumes known),
+//      and whether they are already in nondecreasing order: then b(k) is
+//      nondecreasing too, the scatter and every bucket sort are the
+//      identity, and all later stages are skipped for one copy (with a
+//      declared range the bucket histogram finds the order instead);
 //   2. the histogram of the exact bucket index b(k) = floor((k-min)*B/R);
 //   3. offsets: where every bucket starts in the concatenation (exclusive
 //      scan of the histogram) -- concatenation costs no data movement;
@@ -42,9 +46,14 @@ constexpr uint64_t WINDOW_AVG = 64;       // below this many keys per bucket, wi
 template <typename K>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restrict__ keys, uint64_t n,
                                                                const uint64_t *__restrict__ minmax, uint32_t B,
-                                                               uint32_t passes, uint32_t *__restrict__ subhist)
+                                                               uint32_t passes, uint32_t *__restrict__ subhist,
+                                                               const uint64_t *skip, uint64_t *order)
 {
     __shared__ uint32_t s_h[SUBHIST_WORDS];
+    if (skip && *skip) return;   // keys already sorted
+    // with `order`, also whether the keys are already sorted
+    const bool check = order != nullptr;
+    bool order_ok = true;
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS) s_h[i] = 0;
     __syncthreads();
@@ -59,11 +68,19 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
     const uint64_t stride = (uint64_t)gridDim.x * BK_THREADS;
     for (uint64_t v = (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; v < nvec; v += stride) {
         const Vec x = vk[v];
+        if (check && !vector_in_order<K, KPV>(x.v, keys, v, nvec)) order_ok = false;
 #pragma unroll
         for (int e = 0; e < KPV; e++) count(x.v[e]);
     }
-    for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; i < n; i += stride) count(keys[i]);
-    __syncthreads();
+    for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; i < n; i += stride) {
+        count(keys[i]);
+        if (check && i > 0 && keys[i] < keys[i - 1]) order_ok = false;
+    }
+    if (check) {
+        if (__syncthreads_or(!order_ok) && threadIdx.x == 0) *order = 0;
+    } else {
+        __syncthreads();
+    }
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS)
         if (s_h[i]) atomicAdd(&subhist[i], s_h[i]);
 }
@@ -79,6 +96,7 @@ struct BucketPlanArgs {
     uint32_t B, radix, passes;
     uint32_t full;            // counts holds the full histogram
     uint64_t n;
+    const uint64_t *skip;     // nonzero: the keys are already sorted, no pass runs
 };
 
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
@@ -86,6 +104,11 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
     __shared__ uint32_t s_scan[BK_THREADS / WAVE + 1];
     __shared__ uint32_t s_byte[2 * 256];
     const uint32_t tid = threadIdx.x;
+    if (*a.skip) {
+        if (tid == 0)
+            for (uint32_t q = 0; q < a.passes; q++) a.plan[q * PLAN_WORDS] = 0;
+        return;
+    }
     if (a.full) {
         // bucket starts: exclusive scan of the full histogram (B <= 16384:
         // 64 buckets per thread at most)
@@ -141,8 +164,9 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
 template <typename K>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_bounds(const K *__restrict__ keys, uint64_t n,
                                                               const uint64_t *__restrict__ minmax, uint32_t B,
-                                                              uint64_t *__restrict__ offsets)
+                                                              uint64_t *__restrict__ offsets, const uint64_t *skip)
 {
+    if (*skip) return;   // keys already sorted
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
     const uint64_t stride = (uint64_t)gridDim.x * BK_THREADS;
     for (uint64_t i = (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; i < n; i += stride) {
@@ -228,11 +252,28 @@ __global__ __launch_bounds__(BK_THREADS) void k_suffix_min_apply(uint64_t *offse
     }
 }
 
-// the declared range [0, key_bound] in place of a measured one
-__global__ void k_set_range(uint64_t *minmax, uint64_t lo, uint64_t hi)
+// the declared range [0, key_bound] in place of a measured one; whether
+// the keys are in order is then found by the bucket histogram
+__global__ void k_set_range(uint64_t *minmax, uint64_t lo, uint64_t hi, uint64_t *sorted)
 {
     minmax[0] = lo;
     minmax[1] = hi;
+    *sorted = 1;
+}
+
+// When the keys were already in order, the sort is the identity: the
+// output is a copy of the input (the stages before left it untouched)
+template <typename K>
+__global__ __launch_bounds__(BK_THREADS) void k_copy_if_sorted(const uint64_t *sorted, const K *__restrict__ kin,
+                                                               K *__restrict__ kout, const uint32_t *__restrict__ vin,
+                                                               uint32_t *__restrict__ vout, uint64_t n)
+{
+    if (!*sorted) return;
+    const uint64_t stride = (uint64_t)gridDim.x * BK_THREADS;
+    for (uint64_t i = (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; i < n; i += stride) {
+        if (kout != kin) kout[i] = kin[i];
+        if (vout && vout != vin) vout[i] = vin[i];
+    }
 }
 
 // Windows of consecutive small buckets.  Window g holds the buckets that
@@ -253,6 +294,7 @@ struct WindowSrc {
     uint32_t B;
     uint32_t half;
     uint64_t n;
+    const uint64_t *skip;       // nonzero: keys already sorted, every window empty
     __device__ __forceinline__ uint64_t start_at_or_after(const BucketMap &m, uint64_t p) const
     {
         if (p >= n) return n;
@@ -264,6 +306,15 @@ struct WindowSrc {
     __device__ __forceinline__ void seg(uint64_t g, const KK *&kin, KK *&kout, const uint32_t *&vi, uint32_t *&vo,
                                         uint32_t &mlen, uint32_t &base) const
     {
+        if (*skip) {
+            mlen = 0;
+            base = 0;
+            kin = reinterpret_cast<const KK *>(keys);
+            kout = reinterpret_cast<KK *>(out);
+            vi = vin;
+            vo = vout;
+            return;
+        }
         const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
         const uint64_t lo = start_at_or_after(m, g * half);
         uint64_t hi = start_at_or_after(m, (g + 1) * half);
@@ -303,7 +354,7 @@ BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_
     auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
     L.counters = take((size_t)CTR_WORDS * 4);
     L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
-    L.minmax = take(16);
+    L.minmax = take(24);   // min, max, and whether the keys are already sorted
     L.counts = take(L.buckets <= BUCKET_LDS_HIST_MAX ? (size_t)L.buckets * 4 : 0);
     L.subhist = take((size_t)SUBHIST_WORDS * 4);
     L.excl = take((size_t)L.scatter_passes * radix * 4);
@@ -332,6 +383,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     uint32_t *counters = reinterpret_cast<uint32_t *>(ws + L.counters);
     uint32_t *plan = reinterpret_cast<uint32_t *>(ws + L.plan);
     uint64_t *minmax = reinterpret_cast<uint64_t *>(ws + L.minmax);
+    uint64_t *sorted = minmax + 2;
     uint32_t *counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     uint32_t *subhist = reinterpret_cast<uint32_t *>(ws + L.subhist);
     uint32_t *excl = reinterpret_cast<uint32_t *>(ws + L.excl);
@@ -351,24 +403,39 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     if (tm) tm->start(s);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, counters, (uint64_t)CTR_WORDS, 0u);
     hipError_t e = hipSuccess;
-    if (c.opts.key_bound) hipLaunchKernelGGL(k_set_range, dim3(1), dim3(1), 0, s, minmax, 0ull, c.opts.key_bound);
-    else e = minmax_run((int)sizeof(K), c.keys_in, c.n, minmax, s);
+    // the keys' range and whether they are already in order, found by the
+    // first kernel that reads every key (min/max, or with a declared range
+    // the bucket histogram): then every later stage finds nothing to do and
+    // the output is a copy of the input
+    const bool bound = c.opts.key_bound != 0;
+    if (bound) hipLaunchKernelGGL(k_set_range, dim3(1), dim3(1), 0, s, minmax, 0ull, c.opts.key_bound, sorted);
+    else e = minmax_run((int)sizeof(K), c.keys_in, c.n, minmax, s, sorted);
     if (e != hipSuccess) return e;
+    const uint64_t *hist_skip = bound ? nullptr : sorted;
+    uint64_t *hist_order = bound ? sorted : nullptr;
+    auto copy_if_sorted = [&]() {
+        if (c.keys_in == c.keys_out && (!PAIRS || c.vals_in == c.vals_out)) return;
+        const uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
+        hipLaunchKernelGGL((k_copy_if_sorted<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
+                           s, sorted, static_cast<const K *>(c.keys_in), static_cast<K *>(c.keys_out),
+                           PAIRS ? c.vals_in : nullptr, PAIRS ? c.vals_out : nullptr, c.n);
+    };
     if (tm) tm->mark(INTSORT_KERNEL_MINMAX, 0, s);
     const bool full_hist = B <= BUCKET_LDS_HIST_MAX;
     if (full_hist) {
-        e = bucket_histogram_run((int)sizeof(K), c.keys_in, c.n, minmax, B, counts, s);
+        e = bucket_histogram_run((int)sizeof(K), c.keys_in, c.n, minmax, B, counts, s, hist_skip, hist_order);
     } else {
         hipLaunchKernelGGL(k_fill<uint32_t>, dim3(4), dim3(256), 0, s, subhist, (uint64_t)SUBHIST_WORDS, 0u);
         uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
         hipLaunchKernelGGL((k_bucket_subhist<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
-                           s, static_cast<const K *>(c.keys_in), c.n, minmax, B, L.scatter_passes, subhist);
+                           s, static_cast<const K *>(c.keys_in), c.n, minmax, B, L.scatter_passes, subhist, hist_skip,
+                           hist_order);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     if (tm) tm->mark(INTSORT_KERNEL_BUCKET_HISTOGRAM, 0, s);
     BucketPlanArgs pa{counts, subhist, excl, offsets, plan, B, (uint32_t)C::RADIX, L.scatter_passes,
-                      full_hist ? 1u : 0u, c.n};
+                      full_hist ? 1u : 0u, c.n, sorted};
     hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(BK_THREADS), 0, s, pa);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(fill_grid), dim3(256), 0, s, status0,
                        (uint64_t)L.num_tiles * (C::RADIX + 1), 0u);
@@ -396,15 +463,18 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
                            dim3(C::NT), 0, s, a, dg, tl);
         if (tm) tm->mark(INTSORT_KERNEL_BUCKET_SCATTER, p, s);
     }
+    if (scatter_only) {
+        copy_if_sorted();
+        return hipGetLastError();
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (scatter_only) return hipSuccess;
 
     if (!full_hist) {
         hipLaunchKernelGGL(k_fill<uint64_t>, dim3((B + 256) / 256), dim3(256), 0, s, offsets, (uint64_t)B + 1,
                            (uint64_t)c.n);
         uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
         hipLaunchKernelGGL((k_bucket_bounds<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
-                           s, tmpb, c.n, minmax, B, offsets);
+                           s, tmpb, c.n, minmax, B, offsets, sorted);
         uint64_t *cmin = reinterpret_cast<uint64_t *>(ws + L.suffix);
         const uint32_t chunks = (B + 1 + SUFFIX_CHUNK - 1) / SUFFIX_CHUNK;
         hipLaunchKernelGGL(k_suffix_min_chunks, dim3(chunks), dim3(BK_THREADS), 0, s, offsets, B + 1, cmin);
@@ -423,7 +493,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     if (windows) {
         LdsSortArgs<WindowSrc<K>> la{};
         la.src = WindowSrc<K>{tmpb, static_cast<K *>(c.keys_out), PAIRS ? tmpb_v : nullptr,
-                              PAIRS ? c.vals_out : nullptr, offsets, minmax, B, HALF, c.n};
+                              PAIRS ? c.vals_out : nullptr, offsets, minmax, B, HALF, c.n, sorted};
         la.list = nullptr;
         la.direct_count = (uint32_t)((c.n + HALF - 1) / HALF);
         hipLaunchKernelGGL((k_lds_sort<K, PAIRS, 512, CL::LDS_MAX / 512, WindowSrc<K>>), dim3(la.direct_count),
@@ -443,11 +513,15 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     sc.pairs = PAIRS;
     sc.opts = c.opts;
     sc.opts.digit_bits = 8;
+    sc.opts.flags &= ~INTSORT_FLAG_CHECK_SEGMENTS;   // the bucket starts are computed here, not given
     sc.L = L.S;
     sc.ws = segws;
     sc.timer = tm;
     sc.min_size = windows ? HALF : 0u;   // the windows took these
-    return segmented_sort_run(sc, s);
+    sc.skip = sorted;
+    if ((e = segmented_sort_run(sc, s)) != hipSuccess) return e;
+    copy_if_sorted();
+    return hipGetLastError();
 }
 
 template <typename K, bool PAIRS>

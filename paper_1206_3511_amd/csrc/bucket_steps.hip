@@ -16,22 +16,27 @@ namespace intsort {
 constexpr int MM_THREADS = 1024;
 constexpr int MM_UNROLL = 4;
 
-__global__ void k_minmax_init(uint64_t *minmax)
+__global__ void k_minmax_init(uint64_t *minmax, uint64_t *sorted)
 {
     minmax[0] = ~0ull;
     minmax[1] = 0;
+    if (sorted) *sorted = 1;
 }
 
 // min and max over all keys: per-thread, per-wave, per-workgroup, then one
-// pair of device-wide atomics per workgroup
+// pair of device-wide atomics per workgroup.  With `sorted`, also whether
+// the keys are already in nondecreasing order: a workgroup that sees a key
+// smaller than the one before it clears the flag.
 template <typename K>
 __global__ __launch_bounds__(MM_THREADS) void k_minmax(const K *__restrict__ keys, uint64_t n,
-                                                       uint64_t *__restrict__ minmax)
+                                                       uint64_t *__restrict__ minmax, uint64_t *sorted)
 {
     constexpr int KPV = 16 / (int)sizeof(K);
     struct alignas(16) Vec { K v[KPV]; };
     __shared__ uint64_t s_min[MM_THREADS / WAVE], s_max[MM_THREADS / WAVE];
     K lo = ~K(0), hi = 0;
+    bool order_ok = true;
+    const bool check = sorted != nullptr;
     const uint64_t nvec = n / KPV;
     const Vec *vk = reinterpret_cast<const Vec *>(keys);
     // MM_UNROLL 16-byte loads in flight per thread
@@ -43,7 +48,9 @@ __global__ __launch_bounds__(MM_THREADS) void k_minmax(const K *__restrict__ key
             if (v0 + (uint64_t)u * MM_THREADS < nvec) x[u] = vk[v0 + (uint64_t)u * MM_THREADS];
 #pragma unroll
         for (int u = 0; u < MM_UNROLL; u++) {
-            if (v0 + (uint64_t)u * MM_THREADS < nvec) {
+            const uint64_t v = v0 + (uint64_t)u * MM_THREADS;
+            if (check && !vector_in_order<K, KPV>(x[u].v, keys, v, nvec)) order_ok = false;
+            if (v < nvec) {
 #pragma unroll
                 for (int e = 0; e < KPV; e++) {
                     lo = x[u].v[e] < lo ? x[u].v[e] : lo;
@@ -56,7 +63,9 @@ __global__ __launch_bounds__(MM_THREADS) void k_minmax(const K *__restrict__ key
     for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * MM_THREADS + threadIdx.x; i < n; i += stride) {
         lo = keys[i] < lo ? keys[i] : lo;
         hi = keys[i] > hi ? keys[i] : hi;
+        if (check && i > 0 && keys[i] < keys[i - 1]) order_ok = false;
     }
+    if (check && __syncthreads_or(!order_ok) && threadIdx.x == 0) *sorted = 0;
     uint64_t l = lo, h = hi;
 #pragma unroll
     for (int off = WAVE / 2; off > 0; off >>= 1) {
@@ -78,7 +87,8 @@ __global__ __launch_bounds__(MM_THREADS) void k_minmax(const K *__restrict__ key
     }
 }
 
-hipError_t minmax_run(int key_bytes, const void *keys, uint64_t n, uint64_t *minmax, hipStream_t s)
+hipError_t minmax_run(int key_bytes, const void *keys, uint64_t n, uint64_t *minmax, hipStream_t s,
+                      uint64_t *sorted)
 {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -86,13 +96,13 @@ hipError_t minmax_run(int key_bytes, const void *keys, uint64_t n, uint64_t *min
     const uint64_t cap = (uint64_t)device_cu_count(dev);
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(1), 0, s, minmax);
+    hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(1), 0, s, minmax, sorted);
     if (key_bytes == 4)
         hipLaunchKernelGGL(k_minmax<uint32_t>, dim3((uint32_t)blocks), dim3(MM_THREADS), 0, s,
-                           static_cast<const uint32_t *>(keys), n, minmax);
+                           static_cast<const uint32_t *>(keys), n, minmax, sorted);
     else
         hipLaunchKernelGGL(k_minmax<uint64_t>, dim3((uint32_t)blocks), dim3(MM_THREADS), 0, s,
-                           static_cast<const uint64_t *>(keys), n, minmax);
+                           static_cast<const uint64_t *>(keys), n, minmax, sorted);
     return hipGetLastError();
 }
 
@@ -110,9 +120,15 @@ __global__ void k_zero_u32(uint32_t *p, uint32_t n)
 template <typename K, bool LDS>
 __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__restrict__ keys, uint64_t n,
                                                                  const uint64_t *__restrict__ minmax,
-                                                                 uint32_t B, uint32_t *__restrict__ counts)
+                                                                 uint32_t B, uint32_t *__restrict__ counts,
+                                                                 const uint64_t *skip, uint64_t *order)
 {
     __shared__ uint32_t s_c[LDS ? BH_LDS_BUCKETS : 1];
+    if (skip && *skip) return;   // keys already sorted: nothing to count
+    // with `order`, also whether the keys are already sorted (cleared by a
+    // workgroup that finds a key smaller than the one before it)
+    const bool check = order != nullptr;
+    bool order_ok = true;
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
     if (LDS) {
         for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) s_c[i] = 0;
@@ -136,14 +152,20 @@ __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__rest
             if (v0 + (uint64_t)u * BH_THREADS < nvec) x[u] = vk[v0 + (uint64_t)u * BH_THREADS];
 #pragma unroll
         for (int u = 0; u < BH_UNROLL; u++) {
-            if (v0 + (uint64_t)u * BH_THREADS < nvec) {
+            const uint64_t v = v0 + (uint64_t)u * BH_THREADS;
+            if (check && !vector_in_order<K, KPV>(x[u].v, keys, v, nvec)) order_ok = false;
+            if (v < nvec) {
 #pragma unroll
                 for (int e = 0; e < KPV; e++) count(x[u].v[e]);
             }
         }
     }
     const uint64_t stride = (uint64_t)gridDim.x * BH_THREADS;
-    for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * BH_THREADS + threadIdx.x; i < n; i += stride) count(keys[i]);
+    for (uint64_t i = nvec * KPV + (uint64_t)blockIdx.x * BH_THREADS + threadIdx.x; i < n; i += stride) {
+        count(keys[i]);
+        if (check && i > 0 && keys[i] < keys[i - 1]) order_ok = false;
+    }
+    if (check && __syncthreads_or(!order_ok) && threadIdx.x == 0) *order = 0;
     if (LDS) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) {
@@ -154,7 +176,8 @@ __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__rest
 }
 
 hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, const uint64_t *minmax,
-                                uint32_t B, uint32_t *counts, hipStream_t s)
+                                uint32_t B, uint32_t *counts, hipStream_t s, const uint64_t *skip,
+                                uint64_t *order)
 {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -166,12 +189,12 @@ hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, con
     const bool lds = B <= BH_LDS_BUCKETS;
     if (key_bytes == 4) {
         auto kp = static_cast<const uint32_t *>(keys);
-        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint32_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts);
-        else hipLaunchKernelGGL((k_bucket_histogram<uint32_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts);
+        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint32_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order);
+        else hipLaunchKernelGGL((k_bucket_histogram<uint32_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order);
     } else {
         auto kp = static_cast<const uint64_t *>(keys);
-        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint64_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts);
-        else hipLaunchKernelGGL((k_bucket_histogram<uint64_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts);
+        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint64_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order);
+        else hipLaunchKernelGGL((k_bucket_histogram<uint64_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order);
     }
     return hipGetLastError();
 }

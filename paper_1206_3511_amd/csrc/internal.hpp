@@ -109,9 +109,15 @@ hipError_t radix_sort_run(const RadixCall &c, hipStream_t stream);
 // one-read histogram of all digits into a caller array (uint32 [passes*radix])
 hipError_t digit_histogram_run(const RadixCall &c, uint32_t *counts, hipStream_t stream);
 
-hipError_t minmax_run(int key_bytes, const void *keys, uint64_t n, uint64_t *minmax, hipStream_t s);
+// sorted (optional): set to 1 when the keys are in nondecreasing order, else 0
+hipError_t minmax_run(int key_bytes, const void *keys, uint64_t n, uint64_t *minmax, hipStream_t s,
+                      uint64_t *sorted = nullptr);
+// skip (optional): a device word; when it is nonzero the kernel counts nothing.
+// order (optional): a device word the caller set to 1; cleared unless the
+// keys are in nondecreasing order
 hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, const uint64_t *minmax,
-                                uint32_t num_buckets, uint32_t *counts, hipStream_t s);
+                                uint32_t num_buckets, uint32_t *counts, hipStream_t s,
+                                const uint64_t *skip = nullptr, uint64_t *order = nullptr);
 
 int device_cu_count(int device);
 

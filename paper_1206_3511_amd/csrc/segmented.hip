@@ -54,6 +54,7 @@ struct SegWs {
     uint32_t min_size;        // segments of at most this many keys are left alone
     uint32_t check;           // k_seg_check ran: sort nothing if it found a bad segment
     uint64_t n_total;         // keys of the whole call (the bound of the length sum)
+    const uint64_t *sorted_in; // a device word; nonzero: sort nothing (the input is already in order)
 };
 
 // error-word bit: a segment (or array) the caller described would reach
@@ -98,8 +99,9 @@ __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segm
             prev = dst;
         }
     }
-    // a bad layout found by k_seg_check: no segment is listed, so every
-    // later kernel finds nothing to do
+    // nothing to sort, or a bad layout found by k_seg_check: no segment is
+    // listed, so every later kernel finds nothing to do
+    if (w.sorted_in && *w.sorted_in) return;
     if (w.check) {
         const uint64_t sum = *reinterpret_cast<const uint64_t *>(w.counters + CTR_SEG_SUM);
         const bool bad_sum = sum > w.n_total;
@@ -392,6 +394,7 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     w.min_size = c.min_size;
     w.check = (c.opts.flags & INTSORT_FLAG_CHECK_SEGMENTS) ? 1u : 0u;
     w.n_total = c.n;
+    w.sorted_in = c.skip;
 
     if (tm) tm->start(s);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(1), dim3(256), 0, s, w.counters, (uint64_t)CTR_WORDS, 0u);

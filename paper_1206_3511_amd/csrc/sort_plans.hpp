@@ -61,6 +61,7 @@ struct SegCall {
     char *ws;
     Timer *timer;
     uint32_t min_size;   // segments of at most this many keys are left as they are
+    const uint64_t *skip = nullptr;   // device word: nonzero means sort nothing
 };
 
 SegLayout segmented_layout(int key_bytes, bool pairs, uint64_t n, uint64_t num_segments,

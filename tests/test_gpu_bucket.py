@@ -148,3 +148,59 @@ def test_windows_and_large_buckets_mixed(dtype):
         np.testing.assert_array_equal(host(ok), ref.keys)
         np.testing.assert_array_equal(host(ov), ref.vals)
     assert I.device_error(0) == 0
+
+
+def _sorted_keys(dtype, n, seed):
+    rng = np.random.default_rng(seed)
+    k = np.sort(rand_keys(rng, n, dtype, hi=None if dtype == np.uint32 else 1 << 40))
+    k[: n // 3] = k[0]   # a long run of equal keys
+    return np.maximum(k, 1).astype(dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("B", [1024, 65536])
+@pytest.mark.parametrize("bound", [False, True])
+def test_sorted_input_is_copied(dtype, B, bound):
+    """Keys already in nondecreasing order (found by the min/max kernel, or by
+    the order check with a declared range) skip every stage: the output is
+    the input, values included, also in place and for the scatter alone."""
+    n = 200_003
+    keys = _sorted_keys(dtype, n, B + bound)
+    vals = np.arange(n, dtype=np.uint32)
+    opt = dict(algo="bucket", num_buckets=B, key_bound=int(keys[-1]) + 5 if bound else 0)
+    print(f"sorted input {np.dtype(dtype).name} B={B} bound={bound}", flush=True)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), **opt)
+    np.testing.assert_array_equal(host(ok), keys)
+    np.testing.assert_array_equal(host(ov), vals)
+    np.testing.assert_array_equal(host(I.sort(dev(keys), **opt)), keys)
+    d = dev(keys)
+    I.sort(d, out=d, **opt)
+    np.testing.assert_array_equal(host(d), keys)
+    sk, sv = I.sort_pairs(dev(keys), dev(vals), max_passes=1, **opt)
+    np.testing.assert_array_equal(host(sk), keys)
+    np.testing.assert_array_equal(host(sv), vals)
+    assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("bound", [False, True])
+def test_one_inversion_is_sorted(dtype, bound):
+    """A single key smaller than the one before it, placed where the order
+    check changes hands (inside a 16-byte vector, between lanes, at a wave's
+    first lane, at the next grid step, in the tail past the last whole
+    vector): the check must see it and the full sort run."""
+    n = 200_003
+    kpv = 16 // np.dtype(dtype).itemsize
+    for i in (1, kpv, 64 * kpv, 1024 * 4 * kpv, 1024 * 4 * kpv * 7 + 64 * kpv, n - 1, n // 2 + 1):
+        print(f"one inversion {np.dtype(dtype).name} at {i} bound={bound}", flush=True)
+        keys = _sorted_keys(dtype, n, i)
+        keys[i - 1] = keys[i] + 1 if keys[i] < keys[-1] else keys[i - 1]
+        keys[i] = keys[i - 1] - 1 if keys[i] >= keys[i - 1] else keys[i]
+        assert keys[i] < keys[i - 1]
+        vals = np.arange(n, dtype=np.uint32)
+        opt = dict(algo="bucket", num_buckets=1024, key_bound=int(keys.max()) + 5 if bound else 0)
+        ok, ov = I.sort_pairs(dev(keys), dev(vals), **opt)
+        ref = oracle.radix_lsd(keys, vals)
+        np.testing.assert_array_equal(host(ok), ref.keys)
+        np.testing.assert_array_equal(host(ov), ref.vals)
+        assert I.device_error(0) == 0
