@@ -39,7 +39,6 @@ namespace intsort {
 
 constexpr int BK_THREADS = 256;
 constexpr uint32_t SUBHIST_WORDS = 4 * 256;
-constexpr uint32_t SUFFIX_CHUNK = 4096;   // offsets per workgroup of the suffix minimum
 constexpr uint64_t WINDOW_AVG = 64;       // below this many keys per bucket, windows
 
 // counts of every byte of b(k) that a scatter pass sorts on
@@ -159,96 +158,102 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
     }
 }
 
-// after a two-pass scatter the keys are grouped by bucket: a bucket starts
-// where b changes (offsets were filled with n beforehand)
+// After the scatter the keys are grouped by bucket, in bucket order, so
+// bucket b starts at the first position whose bucket is at least b (an empty
+// bucket where the next nonempty one does, offsets[B] = n).  Position p
+// therefore starts buckets b(p-1)+1 .. b(p), reading b(-1) as -1 and b(n)
+// as B, and every offset has exactly one such position.  The runs of the 64
+// positions of a wave are adjacent, so the wave writes them together: lane t
+// takes the t-th offset of the runs, finds its position by a binary search
+// over the runs' running lengths, and the stores of a wave are contiguous.
+// A run longer than START_RUN (a wide gap of empty buckets) is cut into
+// pieces of START_RUN and listed for k_bucket_start_runs instead.
+constexpr uint64_t START_RUN = 1024;
+constexpr int CTR_START_RUNS = 48;   // counter word: pieces listed
+static_assert(CTR_START_RUNS < CTR_WORDS && CTR_START_RUNS > CTR_ERROR, "a free counter word");
+
+struct StartRun {
+    uint64_t lo, hi, p;   // offsets[lo .. hi) = p
+};
+
+static uint64_t start_run_cap(uint64_t B)
+{
+    // pieces <= (sum of the long runs) / START_RUN + (number of long runs),
+    // both at most (B + 1) / START_RUN
+    return 2 * ((B + 1) / START_RUN) + 2;
+}
+
 template <typename K>
-__global__ __launch_bounds__(BK_THREADS) void k_bucket_bounds(const K *__restrict__ keys, uint64_t n,
+__global__ __launch_bounds__(BK_THREADS) void k_bucket_starts(const K *__restrict__ keys, uint64_t n,
                                                               const uint64_t *__restrict__ minmax, uint32_t B,
-                                                              uint64_t *__restrict__ offsets, const uint64_t *skip)
+                                                              uint64_t *__restrict__ offsets, StartRun *runs,
+                                                              uint32_t *counters, uint64_t run_cap,
+                                                              const uint64_t *skip)
 {
-    if (*skip) return;   // keys already sorted
+    __shared__ uint32_t s_incl[BK_THREADS];
+    __shared__ uint64_t s_lo[BK_THREADS], s_p[BK_THREADS];
+    if (*skip) return;   // keys already sorted: no bucket starts needed
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
+    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    uint32_t *w_incl = s_incl + wave * WAVE;
+    uint64_t *w_lo = s_lo + wave * WAVE, *w_p = s_p + wave * WAVE;
     const uint64_t stride = (uint64_t)gridDim.x * BK_THREADS;
-    for (uint64_t i = (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; i < n; i += stride) {
-        const uint32_t b = bucket_of(m, keys[i]);
-        if (i == 0 || bucket_of(m, keys[i - 1]) != b) offsets[b] = i;
-    }
-}
-
-// An empty bucket starts where the next nonempty one does: offsets[b] =
-// min(offsets[b], offsets[b + 1], ...).  Three launches: the minimum of
-// every chunk of SUFFIX_CHUNK offsets, the minimum over the chunks after each
-// chunk, then the suffix minimum inside every chunk.
-__global__ __launch_bounds__(BK_THREADS) void k_suffix_min_chunks(const uint64_t *offsets, uint32_t count,
-                                                                  uint64_t *cmin)
-{
-    __shared__ uint64_t s_m[BK_THREADS];
-    const uint64_t lo = (uint64_t)blockIdx.x * SUFFIX_CHUNK;
-    uint64_t m = ~0ull;
-    for (uint64_t i = lo + threadIdx.x; i < min((uint64_t)count, lo + SUFFIX_CHUNK); i += BK_THREADS)
-        m = min(m, offsets[i]);
-    s_m[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = BK_THREADS / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) s_m[threadIdx.x] = min(s_m[threadIdx.x], s_m[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) cmin[blockIdx.x] = s_m[0];
-}
-
-// one workgroup: cmin[c] becomes the minimum over the chunks after c
-__global__ __launch_bounds__(1024) void k_suffix_min_carry(uint64_t *cmin, uint32_t chunks)
-{
-    __shared__ uint64_t s_m[1024];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (chunks + 1023) / 1024;
-    const uint32_t lo = tid * per, hi = min(chunks, lo + per);
-    uint64_t run = ~0ull;
-    for (uint32_t i = lo; i < hi; i++) run = min(run, cmin[i]);
-    s_m[tid] = run;
-    __syncthreads();
-    if (tid == 0) {
-        uint64_t r = ~0ull;
-        for (int t = 1023; t >= 0; t--) {
-            const uint64_t x = s_m[t];
-            s_m[t] = r;   // minimum over the threads after t
-            r = min(r, x);
+    // the same trip count for every lane of a wave
+    for (uint64_t base = (uint64_t)blockIdx.x * BK_THREADS + wave * WAVE; base <= n; base += stride) {
+        const uint64_t p = base + lane;
+        uint64_t lo = 0, hi = 0;
+        if (p <= n) {
+            lo = p == 0 ? 0 : (uint64_t)bucket_of(m, keys[p - 1]) + 1;
+            hi = p == n ? (uint64_t)B + 1 : (uint64_t)bucket_of(m, keys[p]) + 1;   // exclusive
         }
-    }
-    __syncthreads();
-    run = s_m[tid];
-    for (uint32_t i = hi; i-- > lo;) {
-        const uint64_t x = cmin[i];
-        cmin[i] = run;
-        run = min(run, x);
+        uint32_t len = 0;
+        if (hi < lo) {   // not grouped by bucket: cannot happen after the scatter
+            atomicOr(&counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
+        } else if (hi - lo <= START_RUN) {
+            len = (uint32_t)(hi - lo);
+        } else {
+            const uint64_t pieces = (hi - lo + START_RUN - 1) / START_RUN;
+            const uint64_t at = atomicAdd(&counters[CTR_START_RUNS], (uint32_t)pieces);
+            for (uint64_t q = 0; q < pieces; q++) {
+                if (at + q >= run_cap) {   // sized so that this cannot happen
+                    atomicOr(&counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
+                    break;
+                }
+                const uint64_t a = lo + q * START_RUN;
+                runs[at + q] = StartRun{a, min(hi, a + START_RUN), p};
+            }
+        }
+        const uint32_t incl = wave_inclusive_scan(len);
+        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+        w_incl[lane] = incl;
+        w_lo[lane] = lo;
+        w_p[lane] = p;
+        wave_sync();
+        for (uint32_t u = lane; u < total; u += WAVE) {
+            // the first lane whose runs end after offset u owns it
+            uint32_t x = 0, y = WAVE - 1;
+            while (x < y) {
+                const uint32_t mid = (x + y) / 2;
+                if (w_incl[mid] > u) y = mid;
+                else x = mid + 1;
+            }
+            const uint32_t before = x > 0 ? w_incl[x - 1] : 0u;
+            offsets[w_lo[x] + (u - before)] = w_p[x];
+        }
+        wave_sync();
     }
 }
 
-__global__ __launch_bounds__(BK_THREADS) void k_suffix_min_apply(uint64_t *offsets, uint32_t count,
-                                                                 const uint64_t *carry)
+// one workgroup per listed piece of a long run of bucket starts
+__global__ __launch_bounds__(BK_THREADS) void k_bucket_start_runs(const StartRun *runs, const uint32_t *counters,
+                                                                  uint64_t run_cap, uint64_t *__restrict__ offsets,
+                                                                  const uint64_t *skip)
 {
-    constexpr uint32_t PER = SUFFIX_CHUNK / BK_THREADS;
-    __shared__ uint64_t s_m[BK_THREADS];
-    const uint32_t tid = threadIdx.x;
-    const uint64_t lo = (uint64_t)blockIdx.x * SUFFIX_CHUNK + (uint64_t)tid * PER;
-    const uint64_t hi = min((uint64_t)count, lo + PER);
-    uint64_t m = ~0ull;
-    for (uint64_t i = lo; i < hi; i++) m = min(m, offsets[i]);
-    s_m[tid] = m;
-    __syncthreads();
-    if (tid == 0) {
-        uint64_t r = carry[blockIdx.x];
-        for (int t = BK_THREADS - 1; t >= 0; t--) {
-            const uint64_t x = s_m[t];
-            s_m[t] = r;   // minimum over everything after thread t's offsets
-            r = min(r, x);
-        }
-    }
-    __syncthreads();
-    uint64_t run = s_m[tid];
-    for (uint64_t i = hi; i-- > lo;) {
-        run = min(run, offsets[i]);
-        offsets[i] = run;
+    if (*skip) return;
+    const uint64_t listed = min((uint64_t)counters[CTR_START_RUNS], run_cap);
+    for (uint64_t r = blockIdx.x; r < listed; r += gridDim.x) {
+        const StartRun e = runs[r];
+        for (uint64_t b = e.lo + threadIdx.x; b < e.hi; b += BK_THREADS) offsets[b] = e.p;
     }
 }
 
@@ -359,7 +364,7 @@ BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_
     L.subhist = take((size_t)SUBHIST_WORDS * 4);
     L.excl = take((size_t)L.scatter_passes * radix * 4);
     L.offsets = take((size_t)(L.buckets + 1) * 8);
-    L.suffix = take((size_t)((L.buckets + 1 + SUFFIX_CHUNK - 1) / SUFFIX_CHUNK) * 8);
+    L.runs = take(L.buckets > BUCKET_LDS_HIST_MAX ? (size_t)start_run_cap(L.buckets) * sizeof(StartRun) : 0);
     L.status0 = take((size_t)L.num_tiles * (radix + 1) * 4);
     L.status1 = take((size_t)L.num_tiles * (radix + 1) * 4);
     L.tmpb_keys = take(n * (size_t)key_bytes);
@@ -470,16 +475,13 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     if (!full_hist) {
-        hipLaunchKernelGGL(k_fill<uint64_t>, dim3((B + 256) / 256), dim3(256), 0, s, offsets, (uint64_t)B + 1,
-                           (uint64_t)c.n);
-        uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
-        hipLaunchKernelGGL((k_bucket_bounds<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
-                           s, tmpb, c.n, minmax, B, offsets, sorted);
-        uint64_t *cmin = reinterpret_cast<uint64_t *>(ws + L.suffix);
-        const uint32_t chunks = (B + 1 + SUFFIX_CHUNK - 1) / SUFFIX_CHUNK;
-        hipLaunchKernelGGL(k_suffix_min_chunks, dim3(chunks), dim3(BK_THREADS), 0, s, offsets, B + 1, cmin);
-        hipLaunchKernelGGL(k_suffix_min_carry, dim3(1), dim3(1024), 0, s, cmin, chunks);
-        hipLaunchKernelGGL(k_suffix_min_apply, dim3(chunks), dim3(BK_THREADS), 0, s, offsets, B + 1, cmin);
+        StartRun *runs = reinterpret_cast<StartRun *>(ws + L.runs);
+        const uint64_t cap = start_run_cap(B);
+        uint64_t blocks = std::min<uint64_t>((c.n + 1 + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
+        hipLaunchKernelGGL((k_bucket_starts<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
+                           s, tmpb, c.n, minmax, B, offsets, runs, counters, cap, (const uint64_t *)sorted);
+        hipLaunchKernelGGL(k_bucket_start_runs, dim3((uint32_t)std::min<uint64_t>(cap, (uint64_t)fill_grid * 4)),
+                           dim3(BK_THREADS), 0, s, runs, counters, cap, offsets, (const uint64_t *)sorted);
         if (tm) tm->mark(INTSORT_KERNEL_PLAN, 1, s);
     }
 

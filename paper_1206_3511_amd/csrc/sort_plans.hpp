@@ -20,7 +20,7 @@ struct SegLayout {
 };
 
 struct BucketLayout {
-    size_t counters, plan, minmax, counts, subhist, excl, offsets, suffix, status0, status1, tmpb_keys, tmpb_vals,
+    size_t counters, plan, minmax, counts, subhist, excl, offsets, runs, status0, status1, tmpb_keys, tmpb_vals,
         seg, total;
     uint32_t buckets, bits, scatter_passes;
     uint64_t num_tiles;

@@ -204,3 +204,35 @@ def test_one_inversion_is_sorted(dtype, bound):
         np.testing.assert_array_equal(host(ok), ref.keys)
         np.testing.assert_array_equal(host(ov), ref.vals)
         assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("case", ["few_values", "two_ends", "one_value_bound"])
+def test_bucket_starts_with_wide_gaps(dtype, case):
+    """More buckets than the on-chip histogram holds, and keys that leave long
+    runs of empty buckets: the bucket starts of those runs are listed in
+    pieces and written by a second kernel.  Unsorted inputs, so no stage is
+    skipped; keys and stable values bit-exact against the oracle."""
+    n = 300_007
+    rng = np.random.default_rng(len(case))
+    top = (1 << 32) - 1 if dtype == np.uint32 else (1 << 40)
+    bound = 0
+    if case == "few_values":          # 50 values spread over the range: gaps of ~40K buckets
+        values = np.sort(rng.integers(0, top, 50, dtype=np.uint64))
+        values[0], values[-1] = 0, top
+        keys = values[rng.integers(0, 50, n)]
+    elif case == "two_ends":          # first and last bucket only
+        keys = np.where(rng.integers(0, 2, n) == 1, top, 0).astype(np.uint64)
+    else:                             # one value in the middle of a declared range
+        keys = np.full(n, top // 2, dtype=np.uint64)
+        keys[::7] = top // 3          # unsorted: two values, alternating runs
+        bound = int(top)
+    keys = keys.astype(dtype)
+    vals = np.arange(n, dtype=np.uint32)
+    B = (1 << 21) + 3
+    print(f"wide gaps {case} {np.dtype(dtype).name} B={B}", flush=True)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=B, key_bound=bound)
+    ref = oracle.radix_lsd(keys, vals)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+    assert I.device_error(0) == 0
