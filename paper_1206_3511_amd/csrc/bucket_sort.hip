@@ -39,6 +39,7 @@ namespace intsort {
 
 constexpr int BK_THREADS = 256;
 constexpr uint32_t SUBHIST_WORDS = 4 * 256;
+constexpr uint32_t SUBHIST_COPIES = 8;     // 32 KB of LDS counts per workgroup
 constexpr uint64_t WINDOW_AVG = 64;       // below this many keys per bucket, windows
 
 // counts of every byte of b(k) that a scatter pass sorts on
@@ -48,17 +49,22 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
                                                                uint32_t passes, uint32_t *__restrict__ subhist,
                                                                const uint64_t *skip, uint64_t *order)
 {
-    __shared__ uint32_t s_h[SUBHIST_WORDS];
+    // SUBHIST_COPIES copies of the counts, lane l adding into copy
+    // l % SUBHIST_COPIES: lanes of one instruction meet on a bank or a word
+    // a few times at most, whatever the keys (sorted runs of a few values
+    // included), where one shared copy serialises them
+    __shared__ uint32_t s_h[SUBHIST_WORDS * SUBHIST_COPIES];
     if (skip && *skip) return;   // keys already sorted
     // with `order`, also whether the keys are already sorted
     const bool check = order != nullptr;
     bool order_ok = true;
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
-    for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS) s_h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS * SUBHIST_COPIES; i += BK_THREADS) s_h[i] = 0;
     __syncthreads();
+    uint32_t *my_h = s_h + threadIdx.x % SUBHIST_COPIES;
     auto count = [&](K k) {
         const uint32_t b = bucket_of(m, k);
-        for (uint32_t p = 0; p < passes; p++) lds_count(s_h + p * 256, (b >> (8 * p)) & 255u);
+        for (uint32_t p = 0; p < passes; p++) atomicAdd(my_h + (p * 256 + ((b >> (8 * p)) & 255u)) * SUBHIST_COPIES, 1u);
     };
     constexpr int KPV = 16 / (int)sizeof(K);
     struct alignas(16) Vec { K v[KPV]; };
@@ -80,8 +86,12 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
     } else {
         __syncthreads();
     }
-    for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS)
-        if (s_h[i]) atomicAdd(&subhist[i], s_h[i]);
+    for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < SUBHIST_COPIES; q++) c += s_h[i * SUBHIST_COPIES + (q + i) % SUBHIST_COPIES];
+        if (c) atomicAdd(&subhist[i], c);
+    }
 }
 
 // One workgroup: exclusive offsets of the scatter digit(s), the bucket
