@@ -80,7 +80,11 @@ typedef enum intsort_key_type {
 
 typedef enum intsort_algo {
     INTSORT_RADIX_LSD = 0, /* Algorithm 4 over a stable per-digit counting sort */
-    INTSORT_BUCKET = 1,    /* Algorithm 2: range, bucket scatter, per-bucket sort */
+    INTSORT_BUCKET = 1,    /* Algorithm 2: range, bucket scatter, per-bucket sort;
+                              keys found already in nondecreasing order by the
+                              first full read (min/max, or with key_bound the
+                              bucket histogram) skip the later steps and are
+                              copied to the output */
     INTSORT_RADIX_MSD = 2  /* most significant digit first (section 2.5's other
                               variant): one stable counting-sort pass on the
                               top r = digit_bits bits of the key, then every one
