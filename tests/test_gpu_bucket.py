@@ -1,7 +1,9 @@
 """GPU parity of bucket sort (HIP path through the C ABI) against the CPU
 oracle: the min/max and bucket-index steps, the stable scatter (buckets
 filled in input order, Algorithm 2 before its per-bucket sort), and the
-final sorted keys and values, bit-exact."""
+final sorted keys and values, bit-exact.  Also the shortcut for keys already
+in order (and single inversions where the order check changes hands), and
+bucket starts across wide gaps of empty buckets."""
 import numpy as np
 import pytest
 
