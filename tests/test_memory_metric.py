@@ -39,3 +39,15 @@ def test_segmented_workspace_counts_segments():
     a = bench._memory(4, False, 1 << 22, 16)
     b = bench._memory(4, False, 1 << 22, 1 << 16)
     assert b["workspace_bytes"] > a["workspace_bytes"]
+
+
+def test_bucket_workspace_holds_bucket_starts():
+    """More buckets than the on-chip histogram holds: the workspace grows by
+    at least the bucket starts (8 bytes for each of B + 1) and the list of
+    long runs of empty buckets (24 bytes for each of 2*floor((B+1)/1024) + 2
+    pieces)."""
+    n = 1 << 20
+    small = bench._memory(4, False, n, algo="bucket", num_buckets=16384)["workspace_bytes"]
+    for B in (1 << 17, 1 << 20, 100_000_000):
+        large = bench._memory(4, False, n, algo="bucket", num_buckets=B)["workspace_bytes"]
+        assert large - small >= 8 * (B - 16384) + 24 * (2 * ((B + 1) // 1024) + 2)
