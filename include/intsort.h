@@ -111,7 +111,8 @@ typedef enum intsort_algo {
                                             check fails, set
                                             INTSORT_DEVERR_BAD_SEGMENTS in the
                                             device error word and sort nothing
-                                            (outputs unspecified) */
+                                            (outputs unspecified); the other
+                                            calls ignore the flag */
 
 /*
  * Options.  A zero field means "library default".
