@@ -420,3 +420,29 @@ def test_full_declared_range_buckets_are_top_bits(dtype, r):
     np.testing.assert_array_equal(res.scat_keys, k[order])
     np.testing.assert_array_equal(res.scat_vals, order.astype(np.uint32))
     np.testing.assert_array_equal(res.counts.astype(np.int64), np.bincount(top, minlength=1 << r))
+
+
+@pytest.mark.parametrize("B", [3, 1024, 1 << 16, 1 << 20])
+def test_bucket_starts_are_first_positions(B):
+    """Bucket b starts at the first position of the scattered array whose
+    bucket is at least b, so an empty bucket starts where the next nonempty
+    one does and offsets[B] = n; equivalently position p starts the buckets
+    b(p-1)+1 .. b(p) (b(-1) = -1, b(n) = B), each exactly once.  Both
+    readings of the concatenation give the oracle's offsets, also across wide
+    gaps of empty buckets (few distinct keys, many buckets)."""
+    n = 3000
+    rng = np.random.default_rng(B)
+    keys = rng.choice(np.array([0, 7, 1 << 20, (1 << 31) + 5, (1 << 32) - 1], dtype=np.uint64), n).astype(np.uint32)
+    res = oracle.bucket(keys, num_buckets=B, want_intermediates=True)
+    mn, mx = int(keys.min()), int(keys.max())
+    bs = np.array([_py_bucket(int(k), mn, mx, B) for k in res.scat_keys], dtype=np.int64)
+    assert np.all(np.diff(bs) >= 0)                        # grouped by bucket, in bucket order
+    first = np.searchsorted(bs, np.arange(B + 1), side="left")
+    np.testing.assert_array_equal(res.offsets, first.astype(res.offsets.dtype))
+    written = np.full(B + 1, -1, dtype=np.int64)
+    ext = np.concatenate([[-1], bs, [B]])
+    for p in range(n + 1):
+        for b in range(ext[p] + 1, ext[p + 1] + 1):
+            assert written[b] == -1                        # one writer per offset
+            written[b] = p
+    np.testing.assert_array_equal(written, res.offsets.astype(np.int64))
