@@ -112,3 +112,20 @@ def test_segmented_equals_per_segment_sort(k, cuts):
             ek, ev = _stable(k[a:b], v[a:b])
             np.testing.assert_array_equal(got_k[a:b], ek)
             np.testing.assert_array_equal(got_v[a:b], ev)
+
+
+@SETTINGS
+@given(inputs(), st.sampled_from([1, 7, 1024, 65536]), st.booleans())
+def test_sorted_input_scatter_is_identity(k, B, bound):
+    """Nondecreasing keys have nondecreasing bucket indices, so the stable
+    scatter by bucket and every bucket's sort leave them in place: bucket
+    sort of sorted keys is the identity, values included (the reasoning
+    behind skipping every stage for already-sorted input)."""
+    k = np.sort(k)
+    v = np.arange(k.size, dtype=np.uint32)
+    kb = int(k.max()) if (bound and k.size) else 0
+    res = oracle.bucket(k, v, num_buckets=B, key_bound=kb, want_intermediates=True)
+    np.testing.assert_array_equal(res.scat_keys, k)
+    np.testing.assert_array_equal(res.scat_vals, v)
+    np.testing.assert_array_equal(res.keys, k)
+    np.testing.assert_array_equal(res.vals, v)
