@@ -141,6 +141,11 @@ def _check(rc: int, where: str):
 def make_options(algo: str | int = "radix", digit_bits: int = 0, num_buckets: int = 0,
                  lds_cutoff: int = 0, max_passes: int = 0, skip_passes: bool = True,
                  key_bound: int = 0, check_segments: bool = False) -> Options:
+    """intsort_options for a call.  Zero fields take the library defaults;
+    skip_passes=False runs every digit pass (INTSORT_FLAG_NO_PASS_SKIP);
+    check_segments=True makes the segmented and batched calls check their
+    segment layout on the device first (INTSORT_FLAG_CHECK_SEGMENTS: a bad
+    layout sets DEVERR_BAD_SEGMENTS in device_error() and sorts nothing)."""
     o = Options()
     lib().intsort_default_options(ctypes.byref(o))
     o.algo = algo if isinstance(algo, int) else {"radix": RADIX, "bucket": BUCKET, "msd": MSD}[algo]
@@ -273,7 +278,9 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, algo: str = "radix", out_
 def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Tensor | None = None,
                    algo: str = "radix", out_keys=None, out_vals=None, stream=None, **opt):
     """Sort every segment [offsets[s], offsets[s+1]) of `keys` on its own.
-    `offsets` is a device uint64/int64 tensor of num_segments + 1 entries."""
+    `offsets` is a device uint64/int64 tensor of num_segments + 1 entries,
+    nondecreasing from 0 to keys.numel(); the host does not read it (pass
+    check_segments=True to have the device check it)."""
     _dev_tensor(keys, "keys")
     _dev_tensor(offsets, "offsets")
     if offsets.dtype not in (torch.uint64, torch.int64):
