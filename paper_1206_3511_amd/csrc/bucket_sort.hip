@@ -89,7 +89,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS) {
         uint32_t c = 0;
 #pragma unroll
-        for (int q = 0; q < SUBHIST_COPIES; q++) c += s_h[i * SUBHIST_COPIES + (q + i) % SUBHIST_COPIES];
+        for (uint32_t q = 0; q < SUBHIST_COPIES; q++) c += s_h[i * SUBHIST_COPIES + (q + i) % SUBHIST_COPIES];
         if (c) atomicAdd(&subhist[i], c);
     }
 }
