@@ -189,3 +189,24 @@ def test_check_segments_flag_accepted(plan_ctx):
     bad.flags = 0x4
     assert I.lib().intsort_workspace_size(plan_ctx.handle, I.U32, 0, 1000, 10, ctypes.byref(bad),
                                           ctypes.byref(b)) == I.ERR_INVALID_ARGUMENT
+
+
+def test_host_tensors_are_refused():
+    """Every step runs in the HIP kernels: host tensors are refused with an
+    error, never sorted on the CPU."""
+    import torch
+    k = torch.arange(100, dtype=torch.int64).flip(0).to(torch.uint32)
+    v = torch.arange(100, dtype=torch.int32).view(torch.uint32)
+    offs = torch.tensor([0, 50, 100], dtype=torch.int64)
+    with pytest.raises(ValueError, match="device tensor"):
+        I.sort(k)
+    with pytest.raises(ValueError, match="device tensor"):
+        I.sort(k, algo="bucket")
+    with pytest.raises(ValueError, match="device tensor"):
+        I.sort_pairs(k, v)
+    with pytest.raises(ValueError, match="device tensor"):
+        I.segmented_sort(k, offs)
+    with pytest.raises(ValueError, match="device tensor"):
+        I.batched_sort([k, k[:10]])
+    with pytest.raises(ValueError, match="device tensor"):
+        I.sort(torch.zeros(4, dtype=torch.int16))
