@@ -47,6 +47,9 @@ MUTANTS = [
      "if (neg_a) return ma > mb;", "if (neg_a) return ma < mb;"),
     ("sign bit of 32-bit keys taken from bit 63",
      "const unsigned top = 8u * (unsigned)key_bytes - 1u;", "const unsigned top = 63u;"),
+    ("bucket starts exported one bucket late",
+     "if (offsets) memcpy(offsets, off, (nbuckets + 1) * sizeof(uint64_t));",
+     "if (offsets) { memcpy(offsets, off + 1, nbuckets * sizeof(uint64_t)); offsets[nbuckets] = n; }"),
     ("ordered merge takes right run on ties",
      "(j < hi && key_before(src[j], src[i], key_bytes, order))",
      "(j < hi && !key_before(src[i], src[j], key_bytes, order))"),
@@ -103,6 +106,12 @@ CHECK = textwrap.dedent(r'''
     res = oracle.bucket(kk, num_buckets=3000, key_bound=10**6, want_intermediates=True)
     want = np.bincount([(3000 * int(x)) // (10**6 + 1) for x in kk], minlength=3000)
     ok &= np.array_equal(res.counts.astype(np.int64), want)
+    # bucket starts: the first position of the scatter whose bucket is at
+    # least b, across wide gaps of empty buckets
+    kk = rng.choice(np.array([0, 7, 1 << 20, (1 << 31) + 5, (1 << 32) - 1], dtype=np.uint64), 500).astype(np.uint32)
+    res = oracle.bucket(kk, num_buckets=4096, want_intermediates=True)
+    bs = np.array([(int(x) * 4096) // (1 << 32) for x in res.scat_keys])
+    ok &= np.array_equal(res.offsets.astype(np.int64), np.searchsorted(bs, np.arange(4097), side="left"))
     # signed keys against the library sort; IEEE keys on a totalOrder ladder
     for dt in (np.int32, np.int64):
         info = np.iinfo(dt)
