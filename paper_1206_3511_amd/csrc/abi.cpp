@@ -92,6 +92,22 @@ bool partial_overlap(const void *a, const void *b, size_t bytes)
     return x < y + bytes && y < x + bytes;
 }
 
+// key-value buffers: values in and out either identical or disjoint, and no
+// key buffer sharing memory with a value buffer
+bool pair_buffers_ok(const void *keys_in, const void *keys_out, const void *vals_in, const void *vals_out,
+                     uint64_t n, int kb)
+{
+    if (partial_overlap(vals_in, vals_out, n * 4)) return false;
+    const void *kbufs[2] = {keys_in, keys_out};
+    const void *vbufs[2] = {vals_in, vals_out};
+    for (auto kp : kbufs)
+        for (auto vp : vbufs) {
+            const uintptr_t k0 = reinterpret_cast<uintptr_t>(kp), v0 = reinterpret_cast<uintptr_t>(vp);
+            if (k0 < v0 + n * 4 && v0 < k0 + n * (size_t)kb) return false;
+        }
+    return true;
+}
+
 intsort_status from_hip(hipError_t e)
 {
     if (e == hipSuccess) return INTSORT_OK;
@@ -138,17 +154,7 @@ intsort_status sort_common(intsort_ctx *ctx, intsort_key_type kt, const void *ke
     if (pairs && (!aligned16(vals_in) || !aligned16(vals_out))) return INTSORT_ERR_MISALIGNED;
     const int kb = key_bytes_of(kt);
     if (partial_overlap(keys_in, keys_out, n * (size_t)kb)) return INTSORT_ERR_INVALID_ARGUMENT;
-    if (pairs) {
-        if (partial_overlap(vals_in, vals_out, n * 4)) return INTSORT_ERR_INVALID_ARGUMENT;
-        // keys and values must not share memory at all
-        const void *kbufs[2] = {keys_in, keys_out};
-        const void *vbufs[2] = {vals_in, vals_out};
-        for (auto kp : kbufs)
-            for (auto vp : vbufs) {
-                const uintptr_t k0 = reinterpret_cast<uintptr_t>(kp), v0 = reinterpret_cast<uintptr_t>(vp);
-                if (k0 < v0 + n * 4 && v0 < k0 + n * (size_t)kb) return INTSORT_ERR_INVALID_ARGUMENT;
-            }
-    }
+    if (pairs && !pair_buffers_ok(keys_in, keys_out, vals_in, vals_out, n, kb)) return INTSORT_ERR_INVALID_ARGUMENT;
     if (n > MAX_KEYS) return INTSORT_ERR_UNSUPPORTED;
     const size_t need = plain_workspace(kb, pairs, n, o);
     if ((st = check_ws(ws, ws_bytes, need)) != INTSORT_OK) return st;
@@ -373,7 +379,8 @@ static intsort_status segmented_common(intsort_ctx *ctx, intsort_key_type kt, co
     if (pairs && (!aligned16(vals_in) || !aligned16(vals_out))) return INTSORT_ERR_MISALIGNED;
     const int kb = key_bytes_of(kt);
     if (partial_overlap(keys_in, keys_out, n_total * (size_t)kb)) return INTSORT_ERR_INVALID_ARGUMENT;
-    if (pairs && partial_overlap(vals_in, vals_out, n_total * 4)) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (pairs && !pair_buffers_ok(keys_in, keys_out, vals_in, vals_out, n_total, kb))
+        return INTSORT_ERR_INVALID_ARGUMENT;
     if (n_total > MAX_KEYS || num_segments > MAX_SEGMENTS) return INTSORT_ERR_UNSUPPORTED;
     const SegLayout L = segmented_layout(kb, pairs, n_total, num_segments, o);
     if ((st = check_ws(ws, ws_bytes, L.total)) != INTSORT_OK) return st;
@@ -509,6 +516,8 @@ intsort_status intsort_bucket_histogram(intsort_ctx *ctx, intsort_key_type kt, c
         if (!ctx || !valid_kt(kt) || !minmax || !counts || num_buckets == 0) return INTSORT_ERR_INVALID_ARGUMENT;
         if (!unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
         if (n > 0 && !keys) return INTSORT_ERR_INVALID_ARGUMENT;
+        // the kernel reads the keys as 16-byte vectors
+        if (n > 0 && !aligned16(keys)) return INTSORT_ERR_MISALIGNED;
         if (num_buckets > MAX_BUCKETS || n >= (1ull << 32)) return INTSORT_ERR_UNSUPPORTED;
         intsort_status st = set_device(ctx);
         if (st != INTSORT_OK) return st;

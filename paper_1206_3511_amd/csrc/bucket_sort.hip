@@ -106,6 +106,8 @@ struct BucketPlanArgs {
     uint32_t full;            // counts holds the full histogram
     uint64_t n;
     const uint64_t *skip;     // nonzero: the keys are already sorted, no pass runs
+    uint32_t in_place;        // the passes write the caller's output, which aliases its
+                              // input (keys or values): start in the scratch buffer
 };
 
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
@@ -113,9 +115,12 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
     __shared__ uint32_t s_scan[BK_THREADS / WAVE + 1];
     __shared__ uint32_t s_byte[2 * 256];
     const uint32_t tid = threadIdx.x;
+    uint32_t *f = a.plan + MAX_PASSES * PLAN_WORDS;   // final-copy words
     if (*a.skip) {
-        if (tid == 0)
+        if (tid == 0) {
             for (uint32_t q = 0; q < a.passes; q++) a.plan[q * PLAN_WORDS] = 0;
+            f[0] = 0;
+        }
         return;
     }
     if (a.full) {
@@ -157,14 +162,23 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
         a.excl[p * a.radix + d] = ex;
     }
     if (tid == 0) {
-        // passes alternate so that the last one lands in the output
+        // passes alternate so that the last one lands in the output; in
+        // place, no pass may read and write one buffer, so they alternate
+        // from the scratch buffer and a copy follows when the last one
+        // lands there
         uint32_t prev = BUF_IN;
         for (uint32_t q = 0; q < a.passes; q++) {
             uint32_t *w = a.plan + q * PLAN_WORDS;
-            const uint32_t dst = ((a.passes - 1 - q) % 2 == 0) ? BUF_OUT : BUF_TMP;
+            uint32_t dst;
+            if (a.in_place) dst = (q % 2 == 0) ? BUF_TMP : BUF_OUT;
+            else dst = ((a.passes - 1 - q) % 2 == 0) ? BUF_OUT : BUF_TMP;
             w[0] = 1; w[1] = prev; w[2] = dst; w[3] = q;
             prev = dst;
         }
+        f[0] = prev == BUF_TMP ? (COPY_KEYS | COPY_VALS) : 0u;
+        f[1] = BUF_TMP;
+        f[2] = BUF_OUT;
+        f[3] = a.passes;
     }
 }
 
@@ -449,8 +463,11 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     }
     if (e != hipSuccess) return e;
     if (tm) tm->mark(INTSORT_KERNEL_BUCKET_HISTOGRAM, 0, s);
+    // only the scatter-only form writes the caller's output (the full sort
+    // scatters into its own buffers)
+    const bool alias = c.keys_in == c.keys_out || (PAIRS && c.vals_in == c.vals_out);
     BucketPlanArgs pa{counts, subhist, excl, offsets, plan, B, (uint32_t)C::RADIX, L.scatter_passes,
-                      full_hist ? 1u : 0u, c.n, sorted};
+                      full_hist ? 1u : 0u, c.n, sorted, scatter_only && alias ? 1u : 0u};
     hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(BK_THREADS), 0, s, pa);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(fill_grid), dim3(256), 0, s, status0,
                        (uint64_t)L.num_tiles * (C::RADIX + 1), 0u);
@@ -479,6 +496,10 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
         if (tm) tm->mark(INTSORT_KERNEL_BUCKET_SCATTER, p, s);
     }
     if (scatter_only) {
+        // in place, an odd number of passes leaves the scatter in scratch
+        const uint64_t blocks = std::min<uint64_t>((c.n + 255) / 256, (uint64_t)fill_grid);
+        hipLaunchKernelGGL((k_plan_final_copy<K, PAIRS>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(256), 0,
+                           s, a.in, a.out, a.tmp, a.vin, a.vout, a.vtmp, plan + MAX_PASSES * PLAN_WORDS, (uint32_t)c.n);
         copy_if_sorted();
         return hipGetLastError();
     }

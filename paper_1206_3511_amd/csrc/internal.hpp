@@ -26,6 +26,10 @@ constexpr uint32_t DEVERR_SCATTER_RANGE = 4u;      // a computed destination fel
 
 // plan words per pass: active, src, dst, ordinal
 constexpr int PLAN_WORDS = 4;
+// final-copy word of a plan (after the passes' words): what moves from the
+// buffer the last pass left it in to the output
+constexpr uint32_t COPY_KEYS = 1u;
+constexpr uint32_t COPY_VALS = 2u;
 constexpr int MAX_PASSES = 16;
 // counters block: tile counters [MAX_PASSES], done counter, error word
 constexpr int CTR_TILE = 0;

@@ -707,4 +707,28 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     }
 }
 
+// Moves a sort's result into the output buffers when its passes left it
+// elsewhere, as the plan's final-copy words f[0..1] say: f[0] & COPY_KEYS
+// moves the keys, f[0] & COPY_VALS the values, from buffer f[1] (the input
+// when no pass ran, else the scratch buffer).  Keys and values are decided
+// apart, because either may be sorted in place while the other is not.
+template <typename K, bool PAIRS>
+__global__ __launch_bounds__(256) void k_plan_final_copy(const K *in, K *out, K *tmp, const uint32_t *vin,
+                                                         uint32_t *vout, uint32_t *vtmp, const uint32_t *f,
+                                                         uint32_t n)
+{
+    const uint32_t what = f[0];
+    if (what == 0) return;
+    const bool from_in = f[1] == BUF_IN;
+    const K *src = from_in ? in : tmp;
+    const uint32_t *vsrc = from_in ? vin : vtmp;
+    const bool keys = (what & COPY_KEYS) != 0;
+    const bool vals = PAIRS && (what & COPY_VALS) != 0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (keys) out[i] = src[i];
+        if (vals) vout[i] = vsrc[i];
+    }
+}
+
 }  // namespace intsort

@@ -75,7 +75,8 @@ struct HistArgs {
     uint32_t n;
     uint32_t max_passes;   // passes allowed to run (<= passes)
     uint32_t skip;         // skip passes whose digit is constant
-    uint32_t in_place;     // keys_in == keys_out
+    uint32_t keys_alias;   // keys_in == keys_out
+    uint32_t vals_alias;   // key-value sort with vals_in == vals_out
     uint32_t finalize;     // 0: only count (step-level entry point), no plan
     uint32_t copies;       // histogram copies the workgroups spread their adds over
     uint32_t *tile_counts; // [tile][radix] first pass: each tile's digit offsets inside its chunk, or null
@@ -283,7 +284,11 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_plan(HistArgs a)
     __syncthreads();
     if (tid == 0) {
         // which passes run, and which buffer each reads and writes: the last
-        // active pass must land in the output buffer
+        // active pass must land in the output buffer.  When either the keys
+        // or the values are sorted in place, no pass may read and write one
+        // buffer, so the first pass goes to the scratch buffer and the
+        // passes alternate from there.
+        const bool in_place = a.keys_alias || a.vals_alias;
         uint32_t act[MAX_PASSES];
         uint32_t A = 0;
         for (int p = 0; p < PASSES; p++) {
@@ -295,16 +300,26 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_plan(HistArgs a)
             uint32_t *w = a.plan + p * PLAN_WORDS;
             if (!act[p]) { w[0] = 0; w[1] = 0; w[2] = 0; w[3] = 0; continue; }
             uint32_t dst;
-            if (a.in_place) dst = (q % 2 == 0) ? BUF_TMP : BUF_OUT;
+            if (in_place) dst = (q % 2 == 0) ? BUF_TMP : BUF_OUT;
             else dst = ((A - 1 - q) % 2 == 0) ? BUF_OUT : BUF_TMP;
             w[0] = 1; w[1] = prev_dst; w[2] = dst; w[3] = q;
             prev_dst = dst;
             q++;
         }
+        // final copy: bit 0 moves the keys, bit 1 the values, from f[1]
         uint32_t *f = a.plan + MAX_PASSES * PLAN_WORDS;
-        if (A == 0) { f[0] = a.in_place ? 0u : 1u; f[1] = BUF_IN; f[2] = BUF_OUT; }
-        else if (prev_dst == BUF_TMP) { f[0] = 1; f[1] = BUF_TMP; f[2] = BUF_OUT; }
-        else { f[0] = 0; f[1] = 0; f[2] = 0; }
+        if (A == 0) {
+            // nothing moved: copy whatever is not already in place
+            f[0] = (a.keys_alias ? 0u : COPY_KEYS) | (a.vals_alias ? 0u : COPY_VALS);
+            f[1] = BUF_IN;
+        } else if (prev_dst == BUF_TMP) {
+            f[0] = COPY_KEYS | COPY_VALS;
+            f[1] = BUF_TMP;
+        } else {
+            f[0] = 0;
+            f[1] = 0;
+        }
+        f[2] = BUF_OUT;
         f[3] = A;
     }
 }
@@ -331,23 +346,6 @@ __global__ __launch_bounds__(256) void k_chunk_sums_scan(uint32_t *sums, const u
         const uint32_t c = sums[(uint64_t)j * radix + d];
         sums[(uint64_t)j * radix + d] = run;
         run += c;
-    }
-}
-
-// ------------------------------------------------------------- final copy
-
-template <typename K, bool PAIRS>
-__global__ __launch_bounds__(256) void k_final_copy(const K *in, K *out, K *tmp, const uint32_t *vin,
-                                                    uint32_t *vout, uint32_t *vtmp, const uint32_t *f,
-                                                    uint32_t n)
-{
-    if (f[0] == 0) return;
-    const K *src = f[1] == BUF_IN ? in : tmp;
-    const uint32_t *vsrc = f[1] == BUF_IN ? vin : vtmp;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        out[i] = src[i];
-        if (PAIRS) vout[i] = vsrc[i];
     }
 }
 
@@ -485,7 +483,8 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
     h.n = (uint32_t)c.n;
     h.max_passes = (uint32_t)c.max_passes;
     h.skip = c.skip_constant_digits ? 1u : 0u;
-    h.in_place = c.keys_in == c.keys_out ? 1u : 0u;
+    h.keys_alias = c.keys_in == c.keys_out ? 1u : 0u;
+    h.vals_alias = c.pairs && c.vals_in == c.vals_out ? 1u : 0u;
     h.finalize = finalize ? 1u : 0u;
     h.copies = copies;
     const uint64_t nvec = c.n / (16 / sizeof(K));
@@ -596,7 +595,7 @@ static hipError_t run_typed(const RadixCall &c, hipStream_t s)
     uint64_t blocks = (c.n + 255) / 256;
     const uint64_t cap = (uint64_t)current_cus() * 4;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL((k_final_copy<K, PAIRS>), dim3((uint32_t)blocks), dim3(256), 0, s, a.in, a.out, a.tmp,
+    hipLaunchKernelGGL((k_plan_final_copy<K, PAIRS>), dim3((uint32_t)blocks), dim3(256), 0, s, a.in, a.out, a.tmp,
                        a.vin, a.vout, a.vtmp, plan + MAX_PASSES * PLAN_WORDS, (uint32_t)c.n);
     if (c.timer) c.timer->mark(INTSORT_KERNEL_COPY, 0, s);
     return hipGetLastError();

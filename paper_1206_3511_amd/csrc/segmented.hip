@@ -278,8 +278,9 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegWs w)
 }
 
 // Moves every large segment whose keys did not end in the output there: all
-// its digits were constant (and the sort is out of place), or in place with
-// an odd number of passes run, which left them in the scratch buffer.
+// its digits were constant (then only what is not sorted in place moves), or
+// its passes ran from the scratch buffer (keys or values in place) and an
+// odd number of them left it there (then keys and values move).
 template <typename K, bool PAIRS, class TilesT>
 __global__ __launch_bounds__(256) void k_seg_final_copy(PassArgs<K> a, TilesT tl)
 {
@@ -291,17 +292,21 @@ __global__ __launch_bounds__(256) void k_seg_final_copy(PassArgs<K> a, TilesT tl
     ti.tmp = a.tmp;
     ti.limit = a.n;
     if (!tl.template get<TILE>(blockIdx.x, ti)) return;
-    const bool in_place = ti.in == ti.out;
-    const uint32_t where = segment_result(tl.slot_mask[ti.slot], in_place);
-    if (where == BUF_OUT || (where == BUF_IN && in_place)) return;
+    const bool keys_alias = ti.in == ti.out;
+    const bool vals_alias = PAIRS && a.vin == a.vout;
+    const uint32_t where = segment_result(tl.slot_mask[ti.slot], keys_alias || vals_alias);
+    if (where == BUF_OUT) return;
+    const bool keys = where == BUF_TMP || !keys_alias;
+    const bool vals = PAIRS && (where == BUF_TMP || !vals_alias);
+    if (!keys && !vals) return;
     const K *src = static_cast<const K *>(where == BUF_IN ? ti.in : ti.tmp);
     K *dst = static_cast<K *>(ti.out);
     const uint32_t *vsrc = where == BUF_IN ? a.vin : a.vtmp;
     for (uint32_t i = threadIdx.x; i < ti.count; i += 256) {
         const uint32_t g = ti.start + i;
         if (g < ti.limit) {
-            dst[g] = src[g];
-            if (PAIRS) a.vout[g] = vsrc[g];
+            if (keys) dst[g] = src[g];
+            if (vals) a.vout[g] = vsrc[g];
         }
     }
 }
@@ -462,7 +467,9 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     tl.num_tiles = w.counters + CTR_SEG_TILES;
     tl.radix = 256u;
     tl.slot_mask = w.slot_mask;
-    tl.in_place = c.keys_in == c.keys_out ? 1u : 0u;
+    // a pass must not read and write one buffer: keys or values in place
+    // route every large segment's passes from the scratch buffer
+    tl.in_place = (c.keys_in == c.keys_out || (PAIRS && c.vals_in == c.vals_out)) ? 1u : 0u;
     set_bufs(tl, w.bufs);
     for (int p = 0; p < PASSES; p++) {
         a.plan = w.plan + p * PLAN_WORDS;

@@ -160,13 +160,19 @@ def make_options(algo: str | int = "radix", digit_bits: int = 0, num_buckets: in
 
 class Context:
     """One intsort context per device (device -1: planning only) and a cached
-    workspace tensor per context."""
+    workspace tensor per stream.
+
+    A workspace must not be used by two calls that run at the same time, so
+    each stream gets its own.  It is allocated while that stream is current:
+    torch's caching allocator then hands its memory to a later allocation
+    only in that stream's order, so dropping it to grow it cannot give it to
+    work on another stream while kernels on its own stream still use it."""
 
     def __init__(self, device: int):
         self.device = device
         self.handle = _vp()
         _check(lib().intsort_create(ctypes.byref(self.handle), device), "intsort_create")
-        self._ws = None
+        self._ws: dict[int, torch.Tensor] = {}
 
     def __del__(self):
         try:
@@ -191,11 +197,18 @@ class Context:
         _check(lib().intsort_timing_read(self.handle, buf, 1024, ctypes.byref(cnt)), "intsort_timing_read")
         return [(KERNEL_KINDS[buf[i].kind], buf[i].index, buf[i].ms) for i in range(cnt.value)]
 
-    def workspace(self, nbytes: int) -> torch.Tensor:
-        if self._ws is None or self._ws.numel() < nbytes:
-            self._ws = None
-            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
-        return self._ws
+    def workspace(self, nbytes: int, stream=None) -> torch.Tensor:
+        """A workspace of at least nbytes for calls on `stream` (None: the
+        current stream)."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        key = s.cuda_stream
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            self._ws.pop(key, None)
+            with torch.cuda.stream(s):
+                ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+            self._ws[key] = ws
+        return ws
 
 
 _contexts: dict[int, Context] = {}
@@ -249,7 +262,7 @@ def sort(keys: torch.Tensor, algo: str = "radix", out: torch.Tensor | None = Non
     o = make_options(algo, **opt)
     n = keys.numel()
     nb = ctx.workspace_size(kt, False, n, 0, o)
-    ws = ctx.workspace(nb)
+    ws = ctx.workspace(nb, stream)
     _check(lib().intsort_sort_keys(ctx.handle, kt, _ptr(keys), _ptr(out), n, ctypes.byref(o), ws.data_ptr(),
                                    ws.numel(), _stream_ptr(stream)), "intsort_sort_keys")
     return out
@@ -268,7 +281,7 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, algo: str = "radix", out_
     ctx = context(keys.device.index)
     o = make_options(algo, **opt)
     n = keys.numel()
-    ws = ctx.workspace(ctx.workspace_size(kt, True, n, 0, o))
+    ws = ctx.workspace(ctx.workspace_size(kt, True, n, 0, o), stream)
     _check(lib().intsort_sort_pairs(ctx.handle, kt, _ptr(keys), _ptr(ok), _ptr(vals), _ptr(ov), n,
                                     ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
            "intsort_sort_pairs")
@@ -291,7 +304,7 @@ def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Tensor
     ctx = context(keys.device.index)
     o = make_options(algo, **opt)
     n = keys.numel()
-    ws = ctx.workspace(ctx.workspace_size(kt, vals is not None, n, max(S, 1), o))
+    ws = ctx.workspace(ctx.workspace_size(kt, vals is not None, n, max(S, 1), o), stream)
     if vals is None:
         _check(lib().intsort_segmented_sort_keys(ctx.handle, kt, _ptr(keys), _ptr(ok), n, S, _ptr(offsets),
                                                  ctypes.byref(o), ws.data_ptr(), ws.numel(),
@@ -325,7 +338,7 @@ def batched_sort(inputs: list, outputs: list | None = None, stream=None) -> list
     total = int(sum(t.numel() for t in inputs))
     ctx = context(dev.index)
     o = make_options("radix")
-    ws = ctx.workspace(ctx.workspace_size(kt, False, total, len(inputs), o))
+    ws = ctx.workspace(ctx.workspace_size(kt, False, total, len(inputs), o), stream)
     _check(lib().intsort_batched_sort_keys(ctx.handle, kt, d_desc.data_ptr(), len(inputs), total, ctypes.byref(o),
                                            ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
            "intsort_batched_sort_keys")
@@ -340,7 +353,7 @@ def digit_histogram(keys: torch.Tensor, digit_bits: int = 8, stream=None) -> tor
     counts = torch.empty(passes * (1 << digit_bits), dtype=torch.uint32, device=keys.device)
     ctx = context(keys.device.index)
     o = make_options("radix", digit_bits=digit_bits)
-    ws = ctx.workspace(ctx.workspace_size(kt, False, 0, 0, o))
+    ws = ctx.workspace(ctx.workspace_size(kt, False, 0, 0, o), stream)
     _check(lib().intsort_digit_histogram(ctx.handle, kt, _ptr(keys), keys.numel(), digit_bits, _ptr(counts),
                                          ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
            "intsort_digit_histogram")
@@ -367,13 +380,16 @@ def bucket_histogram(keys: torch.Tensor, mm: torch.Tensor, num_buckets: int, str
 
 
 def device_error(device: int = 0, stream=None) -> int:
-    """Error word left by the last sort that used this device's cached workspace."""
+    """Error word left by the last sort that used the workspace this device's
+    context keeps for `stream` (None: the current stream)."""
     ctx = context(device)
-    if ctx._ws is None:
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    ws = ctx._ws.get(s.cuda_stream)
+    if ws is None:
         return 0
     w = ctypes.c_uint32(0)
-    _check(lib().intsort_read_device_error(ctx.handle, ctx._ws.data_ptr(), ctx._ws.numel(), ctypes.byref(w),
-                                           _stream_ptr(stream)), "intsort_read_device_error")
+    _check(lib().intsort_read_device_error(ctx.handle, ws.data_ptr(), ws.numel(), ctypes.byref(w),
+                                           _stream_ptr(s)), "intsort_read_device_error")
     return w.value
 
 
@@ -424,7 +440,7 @@ def capture(fn, stream, device: int = 0) -> Graph:
             lib().intsort_graph_destroy(g)
         raise
     _check(lib().intsort_capture_end(ctx.handle, stream.cuda_stream, ctypes.byref(g)), "intsort_capture_end")
-    return Graph(g, device, keep=[ctx._ws])
+    return Graph(g, device, keep=[ctx._ws.get(stream.cuda_stream)])
 
 
 class Server:

@@ -210,3 +210,33 @@ def test_host_tensors_are_refused():
         I.batched_sort([k, k[:10]])
     with pytest.raises(ValueError, match="device tensor"):
         I.sort(torch.zeros(4, dtype=torch.int16))
+
+
+def test_bucket_histogram_requires_aligned_keys(plan_ctx):
+    """The bucket histogram reads keys as 16-byte vectors: an unaligned base is
+    refused before anything is enqueued."""
+    L = I.lib()
+    mm, counts = 0x200000, 0x300000
+    assert L.intsort_bucket_histogram(plan_ctx.handle, I.U32, 0x1004, 100, mm, 1024, counts,
+                                      None) == I.ERR_MISALIGNED
+    assert L.intsort_bucket_histogram(plan_ctx.handle, I.U64, 0x1008, 100, mm, 1024, counts,
+                                      None) == I.ERR_MISALIGNED
+    # aligned keys pass every check and reach the device step
+    assert L.intsort_bucket_histogram(plan_ctx.handle, I.U32, 0x1000, 100, mm, 1024, counts,
+                                      None) == I.ERR_UNSUPPORTED
+
+
+def test_segmented_pairs_refuse_keys_overlapping_values(plan_ctx):
+    L = I.lib()
+    o = I.make_options()
+    n, off = 64, 0x900000
+
+    def call(kin, kout, vin, vout):
+        return L.intsort_segmented_sort_pairs(plan_ctx.handle, I.U32, kin, kout, vin, vout, n, 1, off,
+                                              ctypes.byref(o), 0x1000000, 1 << 30, None)
+
+    assert call(0x1000, 0x2000, 0x3000, 0x4000) == I.ERR_UNSUPPORTED
+    assert call(0x1000, 0x2000, 0x1040, 0x4000) == I.ERR_INVALID_ARGUMENT   # values inside the input keys
+    assert call(0x1000, 0x2000, 0x3000, 0x2000) == I.ERR_INVALID_ARGUMENT   # output values on output keys
+    assert call(0x1000, 0x2000, 0x3000, 0x3010) == I.ERR_INVALID_ARGUMENT   # values partly overlap
+    assert call(0x1000, 0x1000, 0x3000, 0x3000) == I.ERR_UNSUPPORTED        # both in place

@@ -38,6 +38,7 @@ def test_graph_replays_plain_sort(algo, n):
         g.launch(s)
         s.synchronize()
         np.testing.assert_array_equal(host(out), oracle.radix_lsd(a, r=8).keys)
+    assert I.device_error(0, s) == 0
     assert I.device_error(0) == 0
     g.close()
 
