@@ -163,8 +163,14 @@ const char *intsort_status_string(intsort_status s);
 void intsort_default_options(intsort_options *opts);
 
 /*
- * Creates a context bound to HIP device `hip_device` (reads its properties;
- * no device allocation).  *ctx receives the handle; destroy it with
+ * Creates a context bound to HIP device `hip_device` (reads its properties).
+ * The first context of a device also runs, once per process, a short
+ * self-test kernel: the digit passes rank keys stably with LDS atomic adds,
+ * which needs the lanes of one add instruction that hit the same word to be
+ * served in lane order.  The test allocates and frees 4 bytes of device
+ * memory and waits for its kernel; a device that fails it is refused with
+ * INTSORT_ERR_UNSUPPORTED.  The calling thread's current device is left as
+ * it was.  *ctx receives the handle; destroy it with
  * intsort_destroy.  hip_device = -1 makes a planning context that touches no
  * device: workspace sizes and argument checks work on it, and a sort call
  * whose arguments pass the checks returns INTSORT_ERR_UNSUPPORTED.

@@ -242,6 +242,19 @@ intsort_status intsort_create(intsort_ctx **ctx, int hip_device)
         if (!c) return INTSORT_ERR_INTERNAL;
         c->device = hip_device;
         c->cus = hip_device >= 0 ? device_cu_count(hip_device) : 0;
+        if (hip_device >= 0) {
+            // once per device: the pass kernel's stable rank needs LDS atomics
+            // that serve the lanes of one instruction in lane order
+            int prev = 0;
+            bool lane_order = false;
+            const bool ran = hipGetDevice(&prev) == hipSuccess && hipSetDevice(hip_device) == hipSuccess &&
+                             rank_check(hip_device, &lane_order) == hipSuccess;
+            hipSetDevice(prev);
+            if (!ran || !lane_order) {
+                delete c;
+                return ran ? INTSORT_ERR_UNSUPPORTED : INTSORT_ERR_HIP;
+            }
+        }
         *ctx = c;
         return INTSORT_OK;
     } catch (...) {

@@ -47,15 +47,19 @@ __device__ __forceinline__ void store_agent(uint32_t *p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// inclusive scan across the 64 lanes of a wave
+// inclusive scan across the 64 lanes of a wave (every lane active): sums
+// inside rows of 16 lanes by shifted DPP adds, then each row adds the total of
+// the rows before it through the row broadcasts of lanes 15 and 31
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x)
 {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        uint32_t y = __shfl_up(x, off, WAVE);
-        if (lane >= (uint32_t)off) x += y;
-    }
+    // DPP controls: row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 = 0x143;
+    // lanes without a source (or in rows the row mask leaves out) add 0
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
     return x;
 }
 

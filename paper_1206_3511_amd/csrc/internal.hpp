@@ -125,6 +125,11 @@ hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, con
 
 int device_cu_count(int device);
 
+// Runs the lane-order self-test of LDS atomics on a device once (the HIP
+// device must be current) and says whether the device passed: the pass
+// kernel's stable rank needs it.
+hipError_t rank_check(int device, bool *ok);
+
 }  // namespace intsort
 
 struct intsort_ctx;

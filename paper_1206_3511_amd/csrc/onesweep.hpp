@@ -357,6 +357,27 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, uint32_t *wcnt, uint64
     return r;
 }
 
+// Stable rank of one slot of a wave (64 keys, one per lane, in lane order)
+// among the keys the wave has ranked so far, by one LDS atomic add per key on
+// the wave's counter of the key's digit: the lanes of one add instruction
+// that hit the same counter are served in lane order (intsort_create checks
+// this on its device), so the old value an add returns counts the same-digit
+// keys of the earlier slots plus the lanes below with the same digit.  A
+// slot whose lanes all hold one digit adds once for all of them (adds on one
+// word from many lanes are served one after another).
+__device__ __forceinline__ uint32_t wave_rank_atomic(uint32_t d, uint32_t *wcnt)
+{
+    const uint32_t d0 = first_lane_value(d);
+    const uint64_t act = ballot(true);
+    if (ballot(d != d0) == 0) {
+        const uint32_t below = mbcnt(act);
+        uint32_t c = 0;
+        if (below == 0) c = atomicAdd(&wcnt[d0], popc64(act));
+        return first_lane_value(c) + below;
+    }
+    return atomicAdd(&wcnt[d], 1u);
+}
+
 // ---------------------------------------------------------------- look-back
 
 // Sum of the counts of digit d in tiles first_tile .. tile-1 of one segment.
@@ -476,9 +497,7 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     using C = PassCfg<K, BITS>;
     constexpr int RADIX = C::RADIX, NT = C::NT, WAVES = C::WAVES, IPT = C::IPT, TILE = C::TILE;
     constexpr uint32_t MASK = RADIX - 1;
-    constexpr int BM = BITS > 8 ? 256 : RADIX;          // peer bitmap words per wave
     constexpr int DPT = RADIX > NT ? RADIX / NT : 1;    // digits per thread in digit phases
-    static_assert(TILE * sizeof(K) >= WAVES * BM * sizeof(uint64_t), "bitmaps alias the stage");
     static_assert(RADIX <= NT * DPT, "digit phase covers every digit");
 
     __shared__ alignas(16) unsigned char s_raw[TILE * sizeof(K)];
@@ -487,7 +506,6 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     __shared__ uint32_t s_scan[NT / WAVE + 1];
     __shared__ uint32_t s_tile;
     K *s_stage = reinterpret_cast<K *>(s_raw);
-    uint64_t *s_bits = reinterpret_cast<uint64_t *>(s_raw);
 
     if (a.plan[0] == 0) return;   // pass skipped: the same for every workgroup
     uint32_t srcc = a.plan[1], dstc = a.plan[2];
@@ -537,7 +555,6 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         vdst = dstc == BUF_OUT ? a.vout : a.vtmp;
     }
     for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
-    for (uint32_t i = tid; i < (uint32_t)(WAVES * BM); i += NT) s_bits[i] = 0;
     __syncthreads();
     const K *src = static_cast<const K *>(srcc == BUF_IN ? ti.in : (srcc == BUF_OUT ? ti.out : ti.tmp));
     K *dst = static_cast<K *>(dstc == BUF_OUT ? ti.out : ti.tmp);
@@ -583,9 +600,8 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     // ---- stable rank inside the wave
     uint32_t rk[IPT];
     uint32_t *wcnt = s_wcnt + wave * RADIX;
-    uint64_t *bits = s_bits + wave * BM;
 #pragma unroll
-    for (int j = 0; j < IPT; j++) rk[j] = wave_rank<BITS>(digit_of(j), wcnt, bits, lane);
+    for (int j = 0; j < IPT; j++) rk[j] = wave_rank_atomic(digit_of(j), wcnt);
     __syncthreads();
 
     // ---- per digit: offsets of every wave inside the tile and the tile's
