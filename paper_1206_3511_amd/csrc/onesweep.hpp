@@ -95,6 +95,9 @@ struct OrderedDigit {
     template <typename K>
     __device__ __forceinline__ uint32_t operator()(K k) const
     {
+        // 32-bit keys: one bit-field extract (mask + 1 is a power of two)
+        if constexpr (sizeof(K) == 4)
+            return __builtin_amdgcn_ubfe((uint32_t)KeyOrder<ORDER>::ordered(k), shift, __popc(mask));
         return digit_at<K>(KeyOrder<ORDER>::ordered(k), shift, mask);
     }
     // bits lo .. lo+w-1 of the digit
@@ -474,6 +477,26 @@ __device__ __forceinline__ uint32_t look_back(const uint32_t *status, const uint
 
 // ---------------------------------------------------------------- the pass
 
+// A raw buffer over the first n 4-byte elements of an array (n < 2^30, so the
+// byte range fits the 32-bit record count).  The fourth descriptor word is
+// the usual one of gfx9 parts (32-bit data format).  A store at a byte offset
+// at or past the range (~0u, say) is dropped by the hardware.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(T *base, uint32_t n)
+{
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<std::remove_const_t<T> *>(base), 0, (int)(n * 4u),
+                                             0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ void buffer_store(__amdgpu_buffer_rsrc_t rs, uint32_t off, T v)
+{
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, (int)off, 0, 0);
+}
+
+
 template <typename K>
 struct PassArgs {
     const K *in;
@@ -662,7 +685,9 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     }
 
     // ---- look-back: the counts of this digit in the earlier tiles of the
-    // segment
+    // segment.  The digit's keys of this tile go to [start, start + count):
+    // one range test per digit stands for a test per key.  4-byte keys keep
+    // byte offsets in s_gbase (the buffer stores below take byte offsets)
 #pragma unroll
     for (int i = 0; i < DPT; i++) {
         const uint32_t d = tid * DPT + i;
@@ -672,7 +697,11 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
                 prefix = look_back<RADIX>(status, tflag, tile, ti.first_tile, d, &a.counters[CTR_ERROR]);
                 store_agent(&status[(uint64_t)tile * RADIX + d], FLAG_INC | (prefix + tcnt[i]));
             }
-            s_gbase[d] = ti.base + ti.excl[d] + (ti.excl2 ? ti.excl2[d] : 0u) + prefix - texcl[i];
+            const uint32_t start = ti.base + ti.excl[d] + (ti.excl2 ? ti.excl2[d] : 0u) + prefix;
+            // padding past the tile's end is counted with the largest digit
+            const uint32_t real = tcnt[i] - (d == MASK ? (uint32_t)TILE - valid : 0u);
+            if ((uint64_t)start + real > n) atomicOr(&a.counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
+            s_gbase[d] = sizeof(K) == 4 ? (start - texcl[i]) << 2 : start - texcl[i];
             store_agent(&status_next[(uint64_t)tile * RADIX + d], 0u);
         }
     }
@@ -682,43 +711,75 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         store_agent(&tflag_next[tile], 0u);
     }
 
-    // ---- contiguous runs of each digit go to their global offsets
+    // ---- contiguous runs of each digit go to their global offsets.
+    // 4-byte elements go through buffer stores whose range is the n
+    // elements of the buffer; a key past the tile's end (only the last tile
+    // of an array or a segment has any) gets an offset past every range, and
+    // the hardware drops its store, so no store needs a branch
     uint32_t dest[PAIRS && !COMPACT ? IPT : 1];   // where each staged key went
     uint32_t dpk[COMPACT ? (IPT + 3) / 4 : 1];     // or its digit, four to a word
     if (COMPACT)
 #pragma unroll
         for (int q = 0; q < (IPT + 3) / 4; q++) dpk[q] = 0;
-    bool bad = false;
+    const uint32_t tid4 = tid * 4u;
+    if constexpr (sizeof(K) == 4) {
+        const auto rs = buffer_rsrc(dst, n);
+        // groups of keys: their stage reads, then their run starts, then
+        // their stores, so that LDS latency is paid once per group (small
+        // groups with values, whose registers are live here)
+        auto write_keys = [&](auto partial) {
+            constexpr int G = COMPACT ? 2 : 8;
+            static_assert(IPT % G == 0, "whole groups");
 #pragma unroll
-    for (int m = 0; m < IPT; m++) {
-        const uint32_t i = m * NT + tid;
-        if (PAIRS && !COMPACT) dest[m] = n;
-        if (i < valid) {
-            const K key = s_stage[i];
-            const uint32_t d = dg(key);
-            const uint32_t g = s_gbase[d] + i;
-            if (COMPACT) dpk[m / 4] |= d << (8 * (m % 4));
-            if (g < n) {
-                dst[g] = key;
-                if (PAIRS && !COMPACT) dest[m] = g;
-            } else {
-                bad = true;
+            for (int m0 = 0; m0 < IPT; m0 += G) {
+                K key[G];
+                uint32_t d[G], off[G];
+#pragma unroll
+                for (int u = 0; u < G; u++) key[u] = s_stage[(m0 + u) * NT + tid];
+#pragma unroll
+                for (int u = 0; u < G; u++) {
+                    d[u] = dg(key[u]) & MASK;
+                    off[u] = s_gbase[d[u]] + tid4 + (uint32_t)((m0 + u) * NT * 4);
+                }
+#pragma unroll
+                for (int u = 0; u < G; u++) {
+                    if (decltype(partial)::value && (m0 + u) * NT + tid >= valid) off[u] = ~0u;
+                    buffer_store(rs, off[u], key[u]);
+                    if (COMPACT) dpk[(m0 + u) / 4] |= d[u] << (8 * ((m0 + u) % 4));
+                }
+            }
+        };
+        if (valid == (uint32_t)TILE) write_keys(std::false_type{});
+        else write_keys(std::true_type{});
+    } else {
+#pragma unroll
+        for (int m = 0; m < IPT; m++) {
+            const uint32_t i = m * NT + tid;
+            if (PAIRS) dest[m] = ~0u;
+            if (i < valid) {
+                const K key = s_stage[i];
+                const uint32_t g = s_gbase[dg(key)] + i;
+                if (g < n) {
+                    dst[g] = key;
+                    if (PAIRS) dest[m] = g << 2;
+                }
             }
         }
     }
-    if (bad) atomicOr(&a.counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
     if (PAIRS) {
         uint32_t *s_v = reinterpret_cast<uint32_t *>(s_raw);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < IPT; j++) s_v[rk[j]] = v[j];
         __syncthreads();
+        // (a branch per value: without it the compiler keeps every value and
+        // offset of the thread in registers at once)
 #pragma unroll
         for (int m = 0; m < IPT; m++) {
             const uint32_t i = m * NT + tid;
             if (i >= valid) continue;
-            const uint32_t g = COMPACT ? s_gbase[(dpk[m / 4] >> (8 * (m % 4))) & 255u] + i : dest[m];
-            if (g < n) vdst[g] = s_v[i];
+            const uint32_t off = COMPACT ? s_gbase[(dpk[m / 4] >> (8 * (m % 4))) & 255u] + (i << 2) : dest[m];
+            if (off < n * 4u) *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(vdst) + off) = s_v[i];
         }
     }
 }
