@@ -109,7 +109,7 @@ def test_bucket_three_and_four_byte_indices(B, n, dtype):
 
 
 @pytest.mark.parametrize("case", range(1, 7))
-@pytest.mark.parametrize("n", [100_003, 1_000_000])
+@pytest.mark.parametrize("n", [100_003, 1_000_000, 10_000_000])
 def test_paper_map_with_declared_bound(case, n):
     """Section 4's cases sorted with section 2.3's map: B = n buckets and the
     declared range [0, M], b(k) = floor(n*k/(M+1)).  The scatter and the
@@ -127,6 +127,25 @@ def test_paper_map_with_declared_bound(case, n):
     out = I.sort(dev(keys), algo="bucket", num_buckets=n, key_bound=M)
     np.testing.assert_array_equal(host(out), ref.keys)
     assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("case", [1, 2, 5])
+def test_paper_map_at_1e8(case):
+    """The paper's largest size, n = 10^8 with B = n buckets over [0, M]:
+    uniform keys below 10^6 (about 100 copies of each value), the same keys
+    sorted, and uniform keys below 10^8.  Sorted pairs equal the oracle's."""
+    n = 100_000_000
+    keys, M = workloads.paper_case(case, n)
+    print(f"paper case {case} n={n} M={M}", flush=True)
+    vals = np.arange(n, dtype=np.uint32)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=n, key_bound=M)
+    gk, gv = host(ok), host(ov)
+    del ok, ov
+    assert I.device_error(0) == 0
+    print(f"paper case {case} n={n}: oracle", flush=True)
+    ref = oracle.bucket(keys, vals, num_buckets=n, key_bound=M)
+    np.testing.assert_array_equal(gk, ref.keys)
+    np.testing.assert_array_equal(gv, ref.vals)
 
 
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64])

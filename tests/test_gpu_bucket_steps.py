@@ -33,10 +33,20 @@ def test_bucket_histogram_parity(dtype, B, hi):
 
 @pytest.mark.parametrize("dtype,mn,mx,B", [(np.uint32, 0, 2**32 - 1, 1024), (np.uint32, 17, 1040, 7),
                                            (np.uint64, 0, 2**64 - 1, 65536), (np.uint64, 2**40 + 3, 2**41, 1000),
-                                           (np.uint32, 5, 5, 3), (np.uint32, 0, 999, 1024)])
+                                           (np.uint32, 5, 5, 3), (np.uint32, 0, 999, 1024),
+                                           # 64-bit ranges above 2^62: the 128-bit correction loop
+                                           (np.uint64, 3, 2**63 + 2**61 + 2, 1000),
+                                           (np.uint64, 3, 2**63 + 2**61 + 2, 65536),
+                                           (np.uint64, 2**64 - 2**62 - 7, 2**64 - 1, 777),
+                                           # R = 2^62 (the double estimate's last range) and 2^62 + 1
+                                           (np.uint64, 0, 2**62 - 1, 1000), (np.uint64, 0, 2**62, 1000),
+                                           (np.uint64, 10, 2**62 + 10, 3), (np.uint64, 5, 2**62 + 4, 65536)])
 def test_bucket_map_at_boundaries(dtype, mn, mx, B):
     """Keys on both sides of every bucket boundary (sampled for large B),
-    plus min and max: the device histogram of these keys equals the oracle's."""
+    plus min and max: the device histogram of these keys equals the oracle's.
+    For 64-bit keys the device takes b(k) from a double estimate with one
+    correction while R <= 2^62 and from a 128-bit correction loop above, so
+    ranges on either side of 2^62 and up to 2^64 are covered."""
     R = mx - mn + 1
     js = range(1, B) if B <= 1024 else list(range(1, 300)) + list(range(B - 300, B))
     ks = [mn, mx]

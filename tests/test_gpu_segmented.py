@@ -87,35 +87,18 @@ def test_in_place_and_all_empty():
     assert out.numel() == 0 and z.size == 0
 
 
-def _seg_hash(a, offsets):
-    h = workloads.mix64(a.astype(np.uint64) * workloads.GAMMA)
-    return np.add.reduceat(h, offsets[:-1].astype(np.int64)) if a.size else h
-
-
 def test_config4_full_batch():
     """10,000 uint32 arrays, sizes log-uniform in [16, 2^20), distributions
-    from the seven of the 100M workload: every segment nondecreasing with the
-    same multiset as its input (order-independent hash), and 200 sampled
-    segments plus the largest compared element by element with the oracle."""
+    from the seven of the 100M workload, sorted in one segmented call: every
+    one of the 10,000 segments equals the oracle's element by element (the
+    oracle sorts each segment on its own, about 9.4e8 keys in all)."""
     keys, offsets = workloads.segmented_keys()
     print(f"config4: {keys.size} keys", flush=True)
     out, _ = _run(keys, offsets)
-    n = keys.size
-    d = np.diff(out.astype(np.int64))
-    starts = offsets[1:-1].astype(np.int64) - 1
-    d[starts[(starts >= 0) & (starts < n - 1)]] = 0
-    assert np.all(d >= 0)
-    sizes = np.diff(offsets.astype(np.int64))
-    nz = sizes > 0
-    hi = _seg_hash(keys, offsets)[nz[:len(offsets) - 1]]
-    ho = _seg_hash(out, offsets)[nz[:len(offsets) - 1]]
-    np.testing.assert_array_equal(hi, ho)
-    rng = np.random.default_rng(4)
-    sample = list(rng.choice(len(sizes), 200, replace=False)) + [int(np.argmax(sizes))]
-    for s in sample:
-        a, b = int(offsets[s]), int(offsets[s + 1])
-        np.testing.assert_array_equal(out[a:b], oracle.radix_lsd(keys[a:b]).keys)
     assert I.device_error(0) == 0
+    print("config4: oracle", flush=True)
+    ref, _ = oracle.segmented(keys, offsets)
+    np.testing.assert_array_equal(out, ref)
 
 
 def test_check_segments_flag():
