@@ -199,6 +199,27 @@ intsort_status intsort_sort_keys(intsort_ctx *ctx, intsort_key_type kt, const vo
                                  void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * intsort_sort_keys with no workspace argument.  Its workspace is the
+ * library's own device array of INTSORT_NOALLOC_SCRATCH_MB MiB, one per
+ * device, whose address intsort_create takes once per device; the array is
+ * held until the process ends.  The call allocates nothing and the caller
+ * still passes keys_in and keys_out (device memory, as for
+ * intsort_sort_keys, with the same argument rules and results).
+ * Errors: those of intsort_sort_keys, and INTSORT_ERR_WORKSPACE_TOO_SMALL
+ * when intsort_workspace_size for the call exceeds the array (radix sort of
+ * 32-bit keys with 8-bit digits fits about 15 million keys, bucket sort
+ * about 7 million).  Every call on one device shares that device's array:
+ * calls that overlap on one device (other streams, other threads) race and
+ * give undefined results; calls in one stream's order are safe.
+ */
+#define INTSORT_NOALLOC_SCRATCH_MB 64
+intsort_status intsort_sort_keys_noalloc(intsort_ctx *ctx, intsort_key_type kt, const void *keys_in,
+                                         void *keys_out, uint64_t n, const intsort_options *opts,
+                                         void *stream);
+
+/*
  * Stable key-value sort (section 2, stability): keys as intsort_sort_keys,
  * and vals_out[i] is the value that travelled with keys_out[i]; among equal
  * keys, values keep their input order.

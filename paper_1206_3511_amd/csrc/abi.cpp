@@ -244,11 +244,13 @@ intsort_status intsort_create(intsort_ctx **ctx, int hip_device)
         c->cus = hip_device >= 0 ? device_cu_count(hip_device) : 0;
         if (hip_device >= 0) {
             // once per device: the pass kernel's stable rank needs LDS atomics
-            // that serve the lanes of one instruction in lane order
+            // that serve the lanes of one instruction in lane order; and the
+            // device address of the no-allocation entry point's workspace
             int prev = 0;
             bool lane_order = false;
             const bool ran = hipGetDevice(&prev) == hipSuccess && hipSetDevice(hip_device) == hipSuccess &&
-                             rank_check(hip_device, &lane_order) == hipSuccess;
+                             rank_check(hip_device, &lane_order) == hipSuccess &&
+                             noalloc_setup(hip_device) == hipSuccess;
             hipSetDevice(prev);
             if (!ran || !lane_order) {
                 delete c;

@@ -130,6 +130,10 @@ int device_cu_count(int device);
 // kernel's stable rank needs it.
 hipError_t rank_check(int device, bool *ok);
 
+// Takes, once per device (the device must be current), the device address of
+// the array intsort_sort_keys_noalloc uses as its workspace.
+hipError_t noalloc_setup(int device);
+
 }  // namespace intsort
 
 struct intsort_ctx;

@@ -34,7 +34,7 @@ DEVERR_BAD_SEGMENTS = 0x8
 
 EXPORTED = (
     "intsort_status_string", "intsort_default_options", "intsort_create", "intsort_destroy",
-    "intsort_workspace_size", "intsort_sort_keys", "intsort_sort_pairs",
+    "intsort_workspace_size", "intsort_sort_keys", "intsort_sort_keys_noalloc", "intsort_sort_pairs",
     "intsort_segmented_sort_keys", "intsort_segmented_sort_pairs", "intsort_digit_histogram",
     "intsort_minmax", "intsort_bucket_histogram", "intsort_read_device_error",
     "intsort_timing_enable", "intsort_timing_read", "intsort_batched_sort_keys",
@@ -94,6 +94,7 @@ def lib():
                                              ctypes.POINTER(ctypes.c_size_t)]
         L.intsort_sort_keys.argtypes = [_vp, _i, _vp, _vp, _u64, ctypes.POINTER(Options), _vp,
                                         ctypes.c_size_t, _vp]
+        L.intsort_sort_keys_noalloc.argtypes = [_vp, _i, _vp, _vp, _u64, ctypes.POINTER(Options), _vp]
         L.intsort_sort_pairs.argtypes = [_vp, _i, _vp, _vp, _vp, _vp, _u64, ctypes.POINTER(Options),
                                          _vp, ctypes.c_size_t, _vp]
         L.intsort_segmented_sort_keys.argtypes = [_vp, _i, _vp, _vp, _u64, _u64, _vp,
@@ -265,6 +266,21 @@ def sort(keys: torch.Tensor, algo: str = "radix", out: torch.Tensor | None = Non
     ws = ctx.workspace(nb, stream)
     _check(lib().intsort_sort_keys(ctx.handle, kt, _ptr(keys), _ptr(out), n, ctypes.byref(o), ws.data_ptr(),
                                    ws.numel(), _stream_ptr(stream)), "intsort_sort_keys")
+    return out
+
+
+def sort_noalloc(keys: torch.Tensor, algo: str = "radix", out: torch.Tensor | None = None, stream=None,
+                 **opt) -> torch.Tensor:
+    """sort() through intsort_sort_keys_noalloc: the library's own device
+    array is the workspace (nothing is allocated for it; `out` is allocated
+    here when not given).  Calls that overlap on one device race."""
+    _dev_tensor(keys, "keys")
+    kt = _key_type(keys)
+    out = torch.empty_like(keys) if out is None else _dev_tensor(out, "out")
+    ctx = context(keys.device.index)
+    o = make_options(algo, **opt)
+    _check(lib().intsort_sort_keys_noalloc(ctx.handle, kt, _ptr(keys), _ptr(out), keys.numel(), ctypes.byref(o),
+                                           _stream_ptr(stream)), "intsort_sort_keys_noalloc")
     return out
 
 
