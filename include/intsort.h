@@ -115,8 +115,14 @@ typedef enum intsort_algo {
                                             calls ignore the flag */
 
 /*
- * Options.  A zero field means "library default".
- *   digit_bits   radix digit width r: 0 (default 8) | 4 | 8 | 11.  The
+ * Options.  A zero digit_bits, num_buckets or lds_cutoff means "tuned": the
+ * value the context's tuning table (intsort_load_tuning) holds for the
+ * context's device, the key width and the size class floor(log2 n) (n_total
+ * for segmented and batched calls), when the table has one and the call can
+ * take it; otherwise the library default given below.  Other zero fields
+ * mean the library default.  A NULL options pointer means all zero.
+ *   digit_bits   radix digit width r: 0 (tuned for plain radix sorts of
+ *                unsigned keys, else 8) | 4 | 8 | 11.  The
  *                number of passes is ceil(key_bits / r) (Algorithm 4's d
  *                for a key of key_bits bits).
  *   num_buckets  bucket sort: number of buckets B, 1..2^30 (default 1024
@@ -158,6 +164,29 @@ typedef struct intsort_ctx intsort_ctx;
 
 /* Human-readable name of a status code; never NULL. */
 const char *intsort_status_string(intsort_status s);
+
+/*
+ * Tuning table of a context (the autotuner's choices, which zero option
+ * fields take; any choice gives the same bytes, only the speed differs).
+ * A text file, one entry per line, tab-separated:
+ *   device key, kind, key bytes (4 | 8), size class, value
+ * with kind "radix" (value: digit_bits), "bucket" (num_buckets) or
+ * "segmented" (lds_cutoff).  The device key is the one intsort_device_key
+ * gives; "*" matches every device (and a planning context, whose key is
+ * empty).  '#' starts a comment line; lines that do not parse, and values a
+ * call cannot take, are ignored.  intsort_create loads the file named by
+ * $INTSORT_TUNE_FILE, else ~/.cache/intsort/tune.tsv, when it exists.
+ * intsort_load_tuning replaces the context's table with the file at `path`
+ * (INTSORT_ERR_INVALID_ARGUMENT if it cannot be read; the table is then
+ * unchanged); path == NULL empties it.  Not thread-safe against calls on the
+ * same context.
+ */
+intsort_status intsort_load_tuning(intsort_ctx *ctx, const char *path);
+
+/* The device key of a context (its device's name, architecture and HIP
+ * runtime version; empty for a planning context) into buf, NUL-terminated;
+ * INTSORT_ERR_INVALID_ARGUMENT when it does not fit in len bytes. */
+intsort_status intsort_device_key(const intsort_ctx *ctx, char *buf, size_t len);
 
 /* Fills *opts with the defaults (radix, 8-bit digits). */
 void intsort_default_options(intsort_options *opts);

@@ -1,21 +1,25 @@
 """Autotuner for the sort library's run-time choices.
 
 It times candidate settings on the device, on synthetic keys of the shape
-asked for, and keeps the fastest in a JSON table keyed by device name, HIP
-version, kind, key width and size class (floor(log2 n)):
+asked for, and keeps the fastest in the library's tuning table: a text file,
+one tab-separated line per entry (device key, kind, key bytes, size class
+floor(log2 n), value), which the C library reads at intsort_create and
+whenever intsort_load_tuning is called.  Zero option fields then take the
+choice:
 
-  radix      digit width r in {4, 8, 11}
-  bucket     number of buckets B
+  radix      digit width r in {4, 8, 11}      (digit_bits)
+  bucket     number of buckets B               (num_buckets)
   segmented  LDS cutoff: segments up to it are sorted by one workgroup in
-             LDS, longer ones by all workgroups
+             LDS, longer ones by all workgroups (lds_cutoff)
 
-The table lives in $INTSORT_TUNE_FILE, else ~/.cache/intsort/tune.json.
-Every candidate produces the same bytes (the sorts are exact), so a choice
-only changes speed; ``tuned_options`` returns {} where nothing was tuned.
+The table lives in $INTSORT_TUNE_FILE, else ~/.cache/intsort/tune.tsv.  The
+device key comes from the library (intsort_device_key), so both sides agree
+on it.  Every candidate produces the same bytes (the sorts are exact), so a
+choice only changes speed; ``tuned_options`` returns {} where nothing was
+tuned.
 """
 from __future__ import annotations
 
-import json
 import math
 import os
 
@@ -26,39 +30,47 @@ from . import intsort as I
 RADIX_BITS = (4, 8, 11)
 BUCKETS = (256, 1024, 4096, 16384, 65536)
 CUTOFFS = (256, 2048, 8192, 16384)
+FIELDS = {"radix": "digit_bits", "bucket": "num_buckets", "segmented": "lds_cutoff"}
 
 
 def table_path() -> str:
-    return os.environ.get("INTSORT_TUNE_FILE", os.path.expanduser("~/.cache/intsort/tune.json"))
+    return os.environ.get("INTSORT_TUNE_FILE", os.path.expanduser("~/.cache/intsort/tune.tsv"))
 
 
 def _device_key(device: int = 0) -> str:
-    return f"{torch.cuda.get_device_name(device)}|hip {torch.version.hip}"
+    return I.context(device).device_key()
 
 
 def size_class(n: int) -> int:
     return int(math.floor(math.log2(max(1, n))))
 
 
-def load() -> dict:
+def load() -> list:
+    """The table's entries: (device key, kind, key bytes, size class, value)."""
+    rows = []
     try:
         with open(table_path()) as f:
-            return json.load(f)
-    except (OSError, ValueError):
-        return {}
+            for line in f:
+                p = line.rstrip("\n").split("\t")
+                if len(p) == 5 and not p[0].startswith("#") and p[1] in FIELDS:
+                    try:
+                        rows.append((p[0], p[1], int(p[2]), int(p[3]), int(p[4])))
+                    except ValueError:
+                        pass
+    except OSError:
+        pass
+    return rows
 
 
-def save(table: dict) -> None:
+def save(rows: list) -> None:
     path = table_path()
-    os.makedirs(os.path.dirname(path), exist_ok=True)
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
-        json.dump(table, f, indent=1, sort_keys=True)
+        f.write("# device key\tkind\tkey bytes\tsize class\tvalue  (intsort tuning table)\n")
+        for r in sorted(rows):
+            f.write("\t".join(str(x) for x in r) + "\n")
     os.replace(tmp, path)
-
-
-def _entry_key(kind: str, width: int, n: int) -> str:
-    return f"{kind}|w{width}|c{size_class(n)}"
 
 
 def _time(fn, reps: int = 5) -> float:
@@ -78,29 +90,30 @@ def _keys(width: int, n: int, device: int):
     return workloads.device_keys(0, n, 99, width, f"cuda:{device}")
 
 
-def _record(kind: str, width: int, n: int, choice: dict, timings: dict, device: int) -> dict:
-    table = load()
-    dev = table.setdefault(_device_key(device), {})
-    dev[_entry_key(kind, width, n)] = {"choice": choice, "ms": timings, "n": n}
-    save(table)
-    return choice
+def _record(kind: str, width: int, n: int, value: int, device: int, reload: bool = True) -> dict:
+    key = _device_key(device)
+    cls = size_class(n)
+    rows = [r for r in load() if not (r[0] == key and r[1] == kind and r[2] == width and r[3] == cls)]
+    rows.append((key, kind, width, cls, int(value)))
+    save(rows)
+    if reload:
+        # the library's context takes the new choice at once
+        I.context(device).load_tuning(table_path())
+    return {FIELDS[kind]: int(value)}
 
 
 def tune_radix(width: int, n: int, device: int = 0) -> dict:
     keys = _keys(width, n, device)
     out = torch.empty_like(keys)
     ms = {r: _time(lambda: I.sort(keys, out=out, digit_bits=r)) for r in RADIX_BITS}
-    best = min(ms, key=ms.get)
-    return _record("radix", width, n, {"digit_bits": best}, {str(k): round(v, 4) for k, v in ms.items()}, device)
+    return _record("radix", width, n, min(ms, key=ms.get), device)
 
 
 def tune_bucket(width: int, n: int, device: int = 0) -> dict:
     keys = _keys(width, n, device)
     out = torch.empty_like(keys)
     ms = {B: _time(lambda: I.sort(keys, out=out, algo="bucket", num_buckets=B)) for B in BUCKETS}
-    best = min(ms, key=ms.get)
-    return _record("bucket", width, n, {"num_buckets": best}, {str(k): round(v, 4) for k, v in ms.items()},
-                   device)
+    return _record("bucket", width, n, min(ms, key=ms.get), device)
 
 
 def tune_segmented(keys: torch.Tensor, offsets: torch.Tensor, device: int = 0) -> dict:
@@ -112,13 +125,14 @@ def tune_segmented(keys: torch.Tensor, offsets: torch.Tensor, device: int = 0) -
         if width == 8 and c > 8192:
             continue
         ms[c] = _time(lambda: I.segmented_sort(keys, offsets, out_keys=out, lds_cutoff=c), reps=3)
-    best = min(ms, key=ms.get)
-    return _record("segmented", width, keys.numel(), {"lds_cutoff": best},
-                   {str(k): round(v, 4) for k, v in ms.items()}, device)
+    return _record("segmented", width, keys.numel(), min(ms, key=ms.get), device)
 
 
 def tuned_options(kind: str, width: int, n: int, device: int = 0) -> dict:
     """The stored choice for this kind, key width and size class, or {}."""
-    dev = load().get(_device_key(device), {})
-    e = dev.get(_entry_key(kind, width, n))
-    return dict(e["choice"]) if e else {}
+    key = _device_key(device)
+    cls = size_class(n)
+    for r in load():
+        if r[0] in (key, "*") and r[1] == kind and r[2] == width and r[3] == cls:
+            return {FIELDS[kind]: r[4]}
+    return {}

@@ -5,15 +5,20 @@
 #include <hip/hip_runtime.h>
 
 #include <new>
+#include <string>
+#include <vector>
 
 #include "intsort.h"
 #include "internal.hpp"
 #include "sort_plans.hpp"
+#include "tuning.hpp"
 
 struct intsort_ctx {
     int device;
     int cus;
     intsort::Timer *timer = nullptr;   // set while per-kernel timing is on
+    std::string dev_key;               // key of the device in the tuning table
+    std::vector<intsort::TuneEntry> tune;   // tuned defaults of zero option fields
 };
 
 int intsort::ctx_device(const intsort_ctx *ctx) { return ctx ? ctx->device : -1; }
@@ -51,15 +56,35 @@ int key_order(intsort_key_type kt)
     return 0;
 }
 
-intsort_status read_opts(const intsort_options *in, intsort_key_type kt, intsort_options *out)
+// The options of a call on n keys (n_total for segmented and batched calls).
+// A zero digit_bits (plain radix sort of unsigned keys), num_buckets (bucket
+// sort) or lds_cutoff (segmented and batched calls) takes the value the
+// context's table holds for its device, the key width and the size class of
+// n, when there is one and a call can take it; otherwise the library default.
+intsort_status read_opts(const intsort_ctx *ctx, const intsort_options *in, intsort_key_type kt, uint64_t n,
+                         bool segmented, intsort_options *out)
 {
-    intsort_default_options(out);
+    *out = intsort_options{};
+    out->struct_size = sizeof(intsort_options);
+    out->algo = INTSORT_RADIX_LSD;
     if (in) {
         if (in->struct_size != sizeof(intsort_options)) return INTSORT_ERR_INVALID_ARGUMENT;
         *out = *in;
     }
     if (out->algo != INTSORT_RADIX_LSD && out->algo != INTSORT_BUCKET && out->algo != INTSORT_RADIX_MSD)
         return INTSORT_ERR_INVALID_ARGUMENT;
+    if (ctx && !ctx->tune.empty() && valid_kt(kt)) {
+        const int w = key_bytes_of(kt);
+        uint32_t v = 0;
+        if (out->digit_bits == 0 && !segmented && out->algo == INTSORT_RADIX_LSD && unsigned_kt(kt) &&
+            tune_lookup(ctx->tune, ctx->dev_key, TUNE_RADIX_BITS, w, n, &v) && (v == 4 || v == 8 || v == 11))
+            out->digit_bits = v;
+        if (out->num_buckets == 0 && out->algo == INTSORT_BUCKET &&
+            tune_lookup(ctx->tune, ctx->dev_key, TUNE_BUCKETS, w, n, &v) && v >= 1 && v <= MAX_BUCKETS)
+            out->num_buckets = v;
+        if (out->lds_cutoff == 0 && segmented && tune_lookup(ctx->tune, ctx->dev_key, TUNE_LDS_CUTOFF, w, n, &v))
+            out->lds_cutoff = v;
+    }
     if (out->digit_bits == 0) out->digit_bits = 8;
     if (out->digit_bits != 4 && out->digit_bits != 8 && out->digit_bits != 11) return INTSORT_ERR_UNSUPPORTED;
     if (out->algo == INTSORT_RADIX_MSD) {
@@ -145,7 +170,7 @@ intsort_status sort_common(intsort_ctx *ctx, intsort_key_type kt, const void *ke
 {
     if (!ctx || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
     intsort_options o;
-    intsort_status st = read_opts(opts_in, kt, &o);
+    intsort_status st = read_opts(ctx, opts_in, kt, n, false, &o);
     if (st != INTSORT_OK) return st;
     if (n == 0) return INTSORT_OK;
     if (!keys_in || !keys_out) return INTSORT_ERR_INVALID_ARGUMENT;
@@ -242,6 +267,10 @@ intsort_status intsort_create(intsort_ctx **ctx, int hip_device)
         if (!c) return INTSORT_ERR_INTERNAL;
         c->device = hip_device;
         c->cus = hip_device >= 0 ? device_cu_count(hip_device) : 0;
+        c->dev_key = tune_device_key(hip_device);
+        // the tuned defaults, when the default table file exists
+        const std::string path = tune_default_path();
+        if (!path.empty()) tune_load(path.c_str(), &c->tune);
         if (hip_device >= 0) {
             // once per device: the pass kernel's stable rank needs LDS atomics
             // that serve the lanes of one instruction in lane order; and the
@@ -326,13 +355,39 @@ intsort_status intsort_destroy(intsort_ctx *ctx)
     return INTSORT_OK;
 }
 
+intsort_status intsort_load_tuning(intsort_ctx *ctx, const char *path)
+{
+    try {
+        if (!ctx) return INTSORT_ERR_INVALID_ARGUMENT;
+        if (!path) {
+            ctx->tune.clear();
+            return INTSORT_OK;
+        }
+        std::vector<TuneEntry> t;
+        if (!tune_load(path, &t)) return INTSORT_ERR_INVALID_ARGUMENT;
+        ctx->tune = std::move(t);
+        return INTSORT_OK;
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_device_key(const intsort_ctx *ctx, char *buf, size_t len)
+{
+    if (!ctx || !buf || len == 0) return INTSORT_ERR_INVALID_ARGUMENT;
+    if (ctx->dev_key.size() + 1 > len) return INTSORT_ERR_INVALID_ARGUMENT;
+    for (size_t i = 0; i < ctx->dev_key.size(); i++) buf[i] = ctx->dev_key[i];
+    buf[ctx->dev_key.size()] = '\0';
+    return INTSORT_OK;
+}
+
 intsort_status intsort_workspace_size(const intsort_ctx *ctx, intsort_key_type kt, int has_values, uint64_t n,
                                       uint64_t num_segments, const intsort_options *opts, size_t *bytes)
 {
     try {
         if (!ctx || !bytes || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
         intsort_options o;
-        intsort_status st = read_opts(opts, kt, &o);
+        intsort_status st = read_opts(ctx, opts, kt, n, num_segments != 0, &o);
         if (st != INTSORT_OK) return st;
         if (n > MAX_KEYS) return INTSORT_ERR_UNSUPPORTED;
         const int kb = key_bytes_of(kt);
@@ -385,7 +440,7 @@ static intsort_status segmented_common(intsort_ctx *ctx, intsort_key_type kt, co
     if (!ctx || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
     if (!unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
     intsort_options o;
-    intsort_status st = read_opts(opts_in, kt, &o);
+    intsort_status st = read_opts(ctx, opts_in, kt, n_total, true, &o);
     if (st != INTSORT_OK) return st;
     if (n_total == 0 || num_segments == 0) return INTSORT_OK;
     if (!d_offsets || !keys_in || !keys_out) return INTSORT_ERR_INVALID_ARGUMENT;
@@ -453,7 +508,7 @@ intsort_status intsort_batched_sort_keys(intsort_ctx *ctx, intsort_key_type kt, 
         if (!ctx || !valid_kt(kt)) return INTSORT_ERR_INVALID_ARGUMENT;
         if (!unsigned_kt(kt)) return INTSORT_ERR_UNSUPPORTED;
         intsort_options o;
-        intsort_status st = read_opts(opts, kt, &o);
+        intsort_status st = read_opts(ctx, opts, kt, total_keys, true, &o);
         if (st != INTSORT_OK) return st;
         if (count == 0 || total_keys == 0) return INTSORT_OK;
         if (!d_descs) return INTSORT_ERR_INVALID_ARGUMENT;

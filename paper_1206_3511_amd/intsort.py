@@ -41,6 +41,7 @@ EXPORTED = (
     "intsort_server_create", "intsort_server_submit", "intsort_server_poll", "intsort_server_completed",
     "intsort_server_drain", "intsort_server_destroy",
     "intsort_capture_begin", "intsort_capture_end", "intsort_graph_launch", "intsort_graph_destroy",
+    "intsort_load_tuning", "intsort_device_key",
 )
 
 KERNEL_KINDS = ("init", "digit_histogram", "pass", "copy", "minmax", "bucket_histogram",
@@ -120,6 +121,8 @@ def lib():
                                                ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
         L.intsort_server_drain.argtypes = [_vp]
         L.intsort_server_destroy.argtypes = [_vp]
+        L.intsort_load_tuning.argtypes = [_vp, ctypes.c_char_p]
+        L.intsort_device_key.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
         L.intsort_timing_enable.argtypes = [_vp, _i]
         L.intsort_timing_read.argtypes = [_vp, ctypes.POINTER(KernelTime), ctypes.c_uint32,
                                           ctypes.POINTER(ctypes.c_uint32)]
@@ -187,6 +190,18 @@ class Context:
         _check(lib().intsort_workspace_size(self.handle, kt, int(has_values), n, num_segments,
                                             ctypes.byref(opts), ctypes.byref(out)), "intsort_workspace_size")
         return out.value
+
+    def load_tuning(self, path: str | None):
+        """Replaces the context's tuning table with the file at `path` (None
+        empties it): zero digit_bits / num_buckets / lds_cutoff take its
+        choices."""
+        _check(lib().intsort_load_tuning(self.handle, None if path is None else path.encode()),
+               "intsort_load_tuning")
+
+    def device_key(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(lib().intsort_device_key(self.handle, buf, 512), "intsort_device_key")
+        return buf.value.decode()
 
     def timing(self, enable: bool = True):
         _check(lib().intsort_timing_enable(self.handle, int(enable)), "intsort_timing_enable")

@@ -7,6 +7,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# the tests set their own options: no tuning table of the user's applies
+os.environ["INTSORT_TUNE_FILE"] = os.path.join(ROOT, "tests", "golden", "no-tuning-table.tsv")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")

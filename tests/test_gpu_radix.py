@@ -166,7 +166,7 @@ def test_scanned_first_pass(case):
     np.testing.assert_array_equal(out, oracle.radix_lsd(keys, r=8).keys)
     assert I.device_error(0) == 0
     # the intermediate array after the first pass alone
-    one = host(I.sort(dev(keys), max_passes=1))
+    one = host(I.sort(dev(keys), digit_bits=8, max_passes=1))
     np.testing.assert_array_equal(one, oracle.radix_lsd(keys, r=8, want_passes=True).pass_keys[0])
 
 
