@@ -7,7 +7,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# the tests set their own options: no tuning table of the user's applies
+# the tests set their own options: the table path names no file, so no
+# tuning table of the user's applies and every zero option takes its default
 os.environ["INTSORT_TUNE_FILE"] = os.path.join(ROOT, "tests", "golden", "no-tuning-table.tsv")
 
 
