@@ -389,8 +389,8 @@ BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_
     L.excl = take((size_t)L.scatter_passes * radix * 4);
     L.offsets = take((size_t)(L.buckets + 1) * 8);
     L.runs = take(L.buckets > BUCKET_LDS_HIST_MAX ? (size_t)start_run_cap(L.buckets) * sizeof(StartRun) : 0);
-    L.status0 = take((size_t)L.num_tiles * (radix + 1) * 4);
-    L.status1 = take((size_t)L.num_tiles * (radix + 1) * 4);
+    L.status0 = take((size_t)L.num_tiles * radix * 4);
+    L.status1 = take((size_t)L.num_tiles * radix * 4);
     L.tmpb_keys = take(n * (size_t)key_bytes);
     L.tmpb_vals = take(pairs ? n * 4 : 0);
     intsort_options so = o;
@@ -470,7 +470,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
                       full_hist ? 1u : 0u, c.n, sorted, scatter_only && alias ? 1u : 0u};
     hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(BK_THREADS), 0, s, pa);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(fill_grid), dim3(256), 0, s, status0,
-                       (uint64_t)L.num_tiles * (C::RADIX + 1), 0u);
+                       (uint64_t)L.num_tiles * C::RADIX, 0u);
     if (tm) tm->mark(INTSORT_KERNEL_PLAN, 0, s);
 
     // the stable scatter by bucket

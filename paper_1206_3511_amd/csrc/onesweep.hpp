@@ -42,11 +42,11 @@ struct PassCfg {
 };
 
 constexpr uint32_t LOOKBACK_SPIN_LIMIT = 1u << 20;
+// status words a look-back reads per round trip: a walk is bound by the
+// round trips, and wider windows made each round trip slower (measured with
+// 4, 8, 16 and 32 on 10^8 keys)
 #ifndef LOOKBACK_WINDOW
 #define LOOKBACK_WINDOW 4
-#endif
-#ifndef LOOKBACK_SPAN
-#define LOOKBACK_SPAN 32
 #endif
 
 // ---------------------------------------------------------------- digits
@@ -388,56 +388,18 @@ __device__ __forceinline__ uint32_t wave_rank_atomic(uint32_t d, uint32_t *wcnt)
 // Every tile publishes, per digit, an aggregate word (its own count) and
 // later an inclusive word (count of all tiles of its segment up to and
 // including it; the first tile of a segment publishes its inclusive word at
-// once); after its inclusive words it also raises a per-tile flag.  The walk
-// first reads the flags of the 64 previous tiles (one load per lane) to find
-// the nearest finished tile, then fetches the status words of the whole span
-// to it in one batch.  The flag is only a hint: the status words alone
-// decide, and when the hint is missing, stale or too far away the walk falls
-// back to reading LOOKBACK_WINDOW words per round trip: aggregates are added
-// and the walk goes on, an inclusive word ends it, an unpublished word is
-// polled again (bounded: on timeout an error bit is set).
+// once).  The walk reads LOOKBACK_WINDOW words per round trip, nearest tile
+// first: aggregates are added and the walk goes on, an inclusive word ends
+// it, an unpublished word is polled again (bounded: on timeout an error bit
+// is set).
 template <int RADIX>
-__device__ __forceinline__ uint32_t look_back(const uint32_t *status, const uint32_t *tflag, uint32_t tile,
-                                              uint32_t first_tile, uint32_t d, uint32_t *err)
+__device__ __forceinline__ uint32_t look_back(const uint32_t *status, uint32_t tile, uint32_t first_tile, uint32_t d,
+                                              uint32_t *err)
 {
     constexpr int W = LOOKBACK_WINDOW;
-    constexpr int SPAN = LOOKBACK_SPAN;
     uint32_t prefix = 0;
     int64_t t = (int64_t)tile - 1;
     const int64_t lo = first_tile;
-    {
-        const int64_t q = (int64_t)tile - 1 - (int64_t)lane_id();
-        const bool f = q >= lo && load_agent(&tflag[q]) != 0u;
-        const uint64_t m = ballot(f);
-        if (m != 0) {
-            // lanes read tiles tile-1, tile-2, ...: the lowest set lane is
-            // the nearest finished tile
-            const int span = __builtin_ctzll(m) + 1;
-            if (span <= SPAN) {
-                uint32_t sw[SPAN];
-#pragma unroll
-                for (int k = 0; k < SPAN; k++)
-                    sw[k] = k < span ? load_agent(&status[(uint64_t)(t - k) * RADIX + d]) : 0u;
-                bool stop = false, done = false;
-                int consumed = 0;
-#pragma unroll
-                for (int k = 0; k < SPAN; k++) {
-                    if (!stop && k < span) {
-                        const uint32_t fl = sw[k] >> FLAG_SHIFT;
-                        if (fl == 0) {
-                            stop = true;
-                        } else {
-                            prefix += sw[k] & COUNT_MASK;
-                            consumed++;
-                            if (fl & 2u) { stop = true; done = true; }
-                        }
-                    }
-                }
-                if (done) return prefix;
-                t -= consumed;
-            }
-        }
-    }
     uint32_t spins = 0;
     while (t >= lo) {
         uint32_t s[W];
@@ -506,7 +468,7 @@ struct PassArgs {
     uint32_t *vout;
     uint32_t *vtmp;
     const uint32_t *plan;   // this pass's plan words: active, src, dst, ordinal
-    uint32_t *status0;      // look-back words (+ tile flags) for even / odd active passes
+    uint32_t *status0;      // look-back words [tile][radix] for even / odd active passes
     uint32_t *status1;
     uint32_t *counters;
     uint32_t n;             // keys in the whole buffer (bound of every store)
@@ -535,9 +497,6 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     const uint32_t ord = a.plan[3];
     uint32_t *status = (ord & 1) ? a.status1 : a.status0;
     uint32_t *status_next = (ord & 1) ? a.status0 : a.status1;
-    // per-tile "inclusive words published" flags follow each status array
-    uint32_t *tflag = status + (uint64_t)a.tile_capacity * RADIX;
-    uint32_t *tflag_next = status_next + (uint64_t)a.tile_capacity * RADIX;
     const auto dg = da.prepare();
 
     const uint32_t tid = threadIdx.x;
@@ -568,7 +527,6 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         // the tile's segment has a constant digit here: nothing moves, but
         // the tile's look-back words for the next pass start clear
         for (uint32_t d = tid; d < (uint32_t)RADIX; d += NT) store_agent(&status_next[(uint64_t)tile * RADIX + d], 0u);
-        if (tid == 0) store_agent(&tflag_next[tile], 0u);
         return;
     }
     const uint32_t *vsrc = nullptr;
@@ -584,6 +542,15 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
     const uint32_t n = ti.limit;
     const uint32_t valid = ti.count;
     const bool first = tile == ti.first_tile;
+    // where each digit's run of the tile would start without the earlier
+    // tiles of the segment: loaded before the keys, so that these loads are
+    // done by the time the look-back needs them
+    uint32_t gofs[DPT];
+#pragma unroll
+    for (int i = 0; i < DPT; i++) {
+        const uint32_t d = tid * DPT + i;
+        gofs[i] = d < (uint32_t)RADIX ? ti.base + ti.excl[d] + (ti.excl2 ? ti.excl2[d] : 0u) : 0u;
+    }
 
     // ---- load: wave-striped, so (wave, item, lane) order is index order.
     // With 32-bit keys, keys, values and ranks in registers at once would not
@@ -694,10 +661,10 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         if (d < (uint32_t)RADIX) {
             uint32_t prefix = 0;
             if (!first) {
-                prefix = look_back<RADIX>(status, tflag, tile, ti.first_tile, d, &a.counters[CTR_ERROR]);
+                prefix = look_back<RADIX>(status, tile, ti.first_tile, d, &a.counters[CTR_ERROR]);
                 store_agent(&status[(uint64_t)tile * RADIX + d], FLAG_INC | (prefix + tcnt[i]));
             }
-            const uint32_t start = ti.base + ti.excl[d] + (ti.excl2 ? ti.excl2[d] : 0u) + prefix;
+            const uint32_t start = gofs[i] + prefix;
             // padding past the tile's end is counted with the largest digit
             const uint32_t real = tcnt[i] - (d == MASK ? (uint32_t)TILE - valid : 0u);
             if ((uint64_t)start + real > n) atomicOr(&a.counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
@@ -706,10 +673,6 @@ __global__ __launch_bounds__((PassCfg<K, BITS>::NT)) void k_onesweep(PassArgs<K>
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        store_agent(&tflag[tile], 1u);
-        store_agent(&tflag_next[tile], 0u);
-    }
 
     // ---- contiguous runs of each digit go to their global offsets.
     // 4-byte elements go through buffer stores whose range is the n

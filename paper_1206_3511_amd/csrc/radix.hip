@@ -40,8 +40,8 @@
 namespace intsort {
 
 constexpr int HIST_THREADS = 256;
-// most first-pass tiles one histogram workgroup counts (its LDS holds a row
-// of digit counts per tile)
+// most first-pass tiles one histogram workgroup counts (a chunk: the scan
+// over chunks is shorter the more tiles each holds)
 constexpr uint32_t FIRST_PASS_TILES_PER_CHUNK = 8;
 #ifndef HIST_UNROLL
 #define HIST_UNROLL 4
@@ -96,30 +96,32 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
     struct alignas(16) Vec { K v[KPV]; };
 
     __shared__ uint32_t s_h[PASSES * RADIX];
-    constexpr bool TILED = PER_TILE && RADIX <= HIST_THREADS;   // tile counts: one thread per digit
-    // first-pass digits of each tile of the workgroup's chunk
-    __shared__ uint32_t s_t[TILED ? FIRST_PASS_TILES_PER_CHUNK * RADIX : 1];
-    // With 32-bit keys the chunk's other digits go to HC copies of their
-    // counts, lane l adding into copy l % HC, two 16-bit counts to a word:
-    // word (p - 1, v / 2, copy) holds digit value v of pass p in half v % 2.
-    // Lanes of one instruction then reach at most two words per bank and at
-    // most two share a word, whatever the digits; a single shared copy
-    // serialises the lanes that meet on a bank or an address.
-    constexpr bool COPIES = TILED && sizeof(K) == 4;
+    constexpr bool TILED = PER_TILE && RADIX <= HIST_THREADS && sizeof(K) == 4;   // one thread per digit
+    // The first-pass digits of the tile being read go to HT copies of its
+    // counts, lane l adding into copy l % HT at word (digit * HT + copy): a
+    // digit costs two integer instructions and one LDS add, and the lanes
+    // of one add meet on a word only when digit and copy agree.  The other
+    // passes' digits count for the whole chunk in HC copies, two 16-bit
+    // counts to a word: word (p - 1, v / 2, copy) holds digit value v of
+    // pass p in half v % 2, so that at most four lanes of an add share a
+    // word even when every lane holds the same digit (sorted or
+    // narrow-range keys).
+    constexpr int HT = 8;
     constexpr int HC = 16;
     constexpr int HALF = RADIX / 2;
-    static_assert(!COPIES || HIST_THREADS % HC == 0, "every copy has the same threads");
+    static_assert(!TILED || HIST_THREADS % HC == 0, "every copy has the same threads");
     // one copy counts at most HIST_THREADS / HC threads' keys of one chunk
-    static_assert(!COPIES || (uint64_t)FIRST_PASS_TILES_PER_CHUNK * PassCfg<K, BITS>::TILE / HC < 65536u,
+    static_assert(!TILED || (uint64_t)FIRST_PASS_TILES_PER_CHUNK * PassCfg<K, BITS>::TILE / HC < 65536u,
                   "16-bit counts cannot overflow");
-    __shared__ uint32_t s_c[COPIES ? (PASSES - 1) * HALF * HC : 1];
+    __shared__ uint32_t s_t[TILED ? RADIX * HT : 1];
+    __shared__ uint32_t s_c[TILED ? (PASSES - 1) * HALF * HC : 1];
 
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < (uint32_t)(PASSES * RADIX); i += HIST_THREADS) s_h[i] = 0;
-    if (TILED)
-        for (uint32_t i = tid; i < (uint32_t)(FIRST_PASS_TILES_PER_CHUNK * RADIX); i += HIST_THREADS) s_t[i] = 0;
-    if (COPIES)
+    if (TILED) {
+        for (uint32_t i = tid; i < (uint32_t)(RADIX * HT); i += HIST_THREADS) s_t[i] = 0;
         for (uint32_t i = tid; i < (uint32_t)((PASSES - 1) * HALF * HC); i += HIST_THREADS) s_c[i] = 0;
+    }
     {
         const uint64_t stride = (uint64_t)gridDim.x * HIST_THREADS;
         for (uint64_t i = (uint64_t)blockIdx.x * HIST_THREADS + tid; i < a.status0_words; i += stride)
@@ -129,68 +131,71 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
 
     const uint32_t n = a.n;
     if constexpr (TILED) if (a.tile_counts) {
-        // one chunk of consecutive first-pass tiles: digit 0 of every key
-        // goes to its tile's row of s_t, the other digits count for the
-        // whole chunk
+        // one chunk of consecutive first-pass tiles, read tile by tile: the
+        // first-pass digits count per tile, the other digits for the chunk
         constexpr uint32_t TILE = PassCfg<K, BITS>::TILE;
-        constexpr uint32_t VPT = TILE / KPV;   // vectors per tile
+        constexpr int VPTH = (int)(TILE / KPV / HIST_THREADS);   // vectors per thread and tile
+        static_assert(TILE % (KPV * HIST_THREADS) == 0, "tiles of whole vectors per thread");
         const uint32_t t0 = blockIdx.x * a.tiles_per_wg;
         const uint32_t t1 = min(a.num_tiles, t0 + a.tiles_per_wg);
-        const uint32_t k0 = t0 * TILE;
-        const uint32_t cnt = min(n, t1 * TILE) - k0;
-        const uint32_t nv = cnt / KPV;
-        const Vec *tv = reinterpret_cast<const Vec *>(keys + k0);
+        uint32_t *my_t = s_t + tid % HT;
         uint32_t *my_c = s_c + tid % HC;
-        auto count_key = [&](K key, uint32_t slot) {
+        auto count_key = [&](K key) {
             const K k = KeyOrder<ORDER>::ordered(key);
-            lds_count(s_t + slot * RADIX, digit_at<K>(k, 0u, MASK));
+            atomicAdd(my_t + digit_at<K>(k, 0u, MASK) * HT, 1u);
 #pragma unroll
             for (int p = 1; p < PASSES; p++) {
                 const uint32_t d = digit_at<K>(k, (uint32_t)(p * BITS), MASK);
-                if constexpr (COPIES)
-                    atomicAdd(my_c + ((p - 1) * HALF + (d >> 1)) * HC, 1u << (16 * (d & 1)));
-                else
-                    lds_count(s_h + p * RADIX, d);
+                atomicAdd(my_c + ((p - 1) * HALF + (d >> 1)) * HC, 1u << (16 * (d & 1)));
             }
         };
-        for (uint32_t v0 = tid; v0 < nv; v0 += HIST_THREADS * HIST_UNROLL) {
-            Vec x[HIST_UNROLL];
+        uint32_t acc = 0;   // thread d < RADIX: digit d's count in the chunk's earlier tiles
+        for (uint32_t t = t0; t < t1; t++) {
+            const uint32_t k0 = t * TILE;
+            const uint32_t cnt = min(n - k0, TILE);
+            if (cnt == TILE) {
+                // every vector of the thread's share of the tile in flight at once
+                const Vec *tv = reinterpret_cast<const Vec *>(keys + k0) + tid;
+                Vec x[VPTH];
 #pragma unroll
-            for (int u = 0; u < HIST_UNROLL; u++)
-                if (v0 + u * HIST_THREADS < nv) x[u] = tv[v0 + u * HIST_THREADS];
+                for (int j = 0; j < VPTH; j++) x[j] = tv[j * HIST_THREADS];
 #pragma unroll
-            for (int u = 0; u < HIST_UNROLL; u++) {
-                const uint32_t v = v0 + u * HIST_THREADS;
-                if (v < nv) {
+                for (int j = 0; j < VPTH; j++)
 #pragma unroll
-                    for (int e = 0; e < KPV; e++) count_key(x[u].v[e], v / VPT);
+                    for (int e = 0; e < KPV; e++) count_key(x[j].v[e]);
+            } else {
+                for (uint32_t i = tid; i < cnt; i += HIST_THREADS) count_key(keys[k0 + i]);
+            }
+            __syncthreads();
+            if (tid < (uint32_t)RADIX) {
+                // the tile's count of digit tid: the sum of its copies (read
+                // from a rotated start, so that the threads spread over the
+                // banks), which start clear for the next tile
+                uint32_t c = 0;
+#pragma unroll
+                for (int q = 0; q < HT; q++) {
+                    const uint32_t w = tid * HT + (q + tid) % HT;
+                    c += s_t[w];
+                    s_t[w] = 0;
                 }
-            }
-        }
-        for (uint32_t i = nv * KPV + tid; i < cnt; i += HIST_THREADS) count_key(keys[k0 + i], i / TILE);
-        __syncthreads();
-        if (tid < (uint32_t)RADIX) {
-            uint32_t acc = 0;
-            for (uint32_t t = t0; t < t1; t++) {
                 a.tile_counts[(uint64_t)t * RADIX + tid] = acc;
-                acc += s_t[(t - t0) * RADIX + tid];
+                acc += c;
             }
-            a.chunk_sums[(uint64_t)blockIdx.x * RADIX + tid] = acc;
-            // digit 0 is counted only in s_t, so its words of s_h are this
-            // thread's alone
-            s_h[tid] += acc;
+            __syncthreads();
         }
-        if constexpr (COPIES) {
-            // the other passes' counts: the sum of the copies (read from a
-            // rotated start, so that the threads spread over the banks)
-            for (uint32_t i = tid; i < (uint32_t)((PASSES - 1) * RADIX); i += HIST_THREADS) {
-                const uint32_t p1 = i / RADIX, v = i % RADIX;
-                const uint32_t *w = s_c + (p1 * HALF + (v >> 1)) * HC;
-                uint32_t sum = 0;
+        if (tid < (uint32_t)RADIX) {
+            a.chunk_sums[(uint64_t)blockIdx.x * RADIX + tid] = acc;
+            s_h[tid] = acc;
+        }
+        // the other passes' counts: the sum of the copies (read from a
+        // rotated start, so that the threads spread over the banks)
+        for (uint32_t i = tid; i < (uint32_t)((PASSES - 1) * RADIX); i += HIST_THREADS) {
+            const uint32_t p1 = i / RADIX, v = i % RADIX;
+            const uint32_t *w = s_c + (p1 * HALF + (v >> 1)) * HC;
+            uint32_t c = 0;
 #pragma unroll
-                for (int c = 0; c < HC; c++) sum += (w[(c + (v >> 1)) % HC] >> (16 * (v & 1))) & 0xffffu;
-                s_h[(p1 + 1) * RADIX + v] = sum;
-            }
+            for (int q = 0; q < HC; q++) c += (w[(q + (v >> 1)) % HC] >> (16 * (v & 1))) & 0xffffu;
+            s_h[RADIX + i] = c;
         }
         __syncthreads();
         uint32_t *hdst = a.hist + (blockIdx.x % a.copies) * (uint32_t)(PASSES * RADIX);
@@ -426,8 +431,8 @@ RadixLayout radix_layout(int key_bytes, bool pairs, uint64_t n, int bits)
         const uint64_t chunks = std::min<uint64_t>(L.num_tiles, ChunkCfg<uint32_t, 11>::MAX_CHUNKS);
         L.status_words = chunks * (uint64_t)L.g.radix;
     } else {
-        // per tile and digit: look-back words, then one flag per tile
-        L.status_words = L.num_tiles * (uint64_t)(L.g.radix + 1);
+        // per tile and digit: one look-back word
+        L.status_words = L.num_tiles * (uint64_t)L.g.radix;
     }
     L.status0 = take((size_t)L.status_words * 4);
     L.status1 = take((size_t)L.status_words * 4);

@@ -185,7 +185,6 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
             w.seg_excl[((uint64_t)(i / 256) * w.slot_cap + d.slot) * 256 + i % 256] = 0;
     for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS) s_h[i] = 0;
     for (uint32_t i = threadIdx.x; i < 256u; i += SEG_HIST_THREADS) w.status0[(uint64_t)t * 256 + i] = 0;
-    if (threadIdx.x == 0) w.status0[(uint64_t)w.tile_cap * 256 + t] = 0;
     __syncthreads();
     // U loads in flight per thread (segments start anywhere, so 4- or
     // 8-byte loads)
@@ -341,8 +340,8 @@ static SegLayout seg_layout_typed(uint64_t n, uint64_t S, uint32_t cutoff_req)
     L.tile_hist = take((size_t)L.tile_cap * PASSES * 256 * 4);
     L.seg_excl = take((size_t)PASSES * L.slot_cap * 256 * 4);
     L.slot_mask = take((size_t)L.slot_cap * 4);
-    L.status0 = take((size_t)L.tile_cap * 257 * 4);
-    L.status1 = take((size_t)L.tile_cap * 257 * 4);
+    L.status0 = take((size_t)L.tile_cap * 256 * 4);
+    L.status1 = take((size_t)L.tile_cap * 256 * 4);
     L.tmp_keys = take(n * sizeof(K));
     L.tmp_vals = take(PAIRS ? n * 4 : 0);
     L.total = off;
