@@ -31,12 +31,16 @@ HBM_PEAK_GBS = 8000.0
 PASS_SOURCES = ("paper_1206_3511_amd/csrc/onesweep.hpp", "paper_1206_3511_amd/csrc/radix.hip",
                 "paper_1206_3511_amd/csrc/device_common.hpp", "paper_1206_3511_amd/csrc/internal.hpp")
 TRAFFIC_FILE = "profiles/onesweep_u32_100M_r8_hbm_traffic.md"
+# longest array the segmented sort of 32-bit keys sorts in one workgroup's
+# LDS when no cutoff is given
+SEG_LDS_MAX_U32 = 16384
 DISTS = ("uniform", "small", "mid", "sorted", "reverse", "swaps", "gaussian")
 
 
 def _workloads():
     w = {"uniform_u32_100M_radix_r8": ("plain", dict(dist=0, n=100_000_000, algo="radix", bits=8, B=0))}
     w["config1_u32_1M_radix_r8"] = ("plain", dict(dist=0, n=1_000_000, algo="radix", bits=8, B=0))
+    w["uniform_u32_100M_radix_r11"] = ("plain", dict(dist=0, n=100_000_000, algo="radix", bits=11, B=0))
     w["config1_u32_1M_bucket_B1024"] = ("plain", dict(dist=0, n=1_000_000, algo="bucket", bits=8, B=1024))
     for e, n in ((6, 1_000_000), (7, 10_000_000), (8, 100_000_000)):
         w[f"uniform_u32_1e{e}_msd_r8"] = ("plain", dict(dist=0, n=n, algo="msd", bits=8, B=0))
@@ -61,6 +65,7 @@ def _workloads():
 
 
 WORKLOADS = _workloads()
+HEADLINE = "uniform_u32_100M_radix_r8"
 
 
 _STEPS_MS = []   # per-step times of the last _timed call
@@ -269,7 +274,9 @@ def run_plain(name, p, args):
         passes = -(-32 // bits)
         per_pass = 2 * n * w
         total = n * w + passes * per_pass
-        roof = _roofline("k_onesweep (one digit pass)", per_pass, avg.get("pass", float("nan")),
+        kname = "k_chunk_count + k_chunk_scan + k_chunk_sort (one 11-bit digit pass)" if bits == 11 else \
+            "k_onesweep (one digit pass)"
+        roof = _roofline(kname, per_pass, avg.get("pass", float("nan")),
                          {"traffic": measured_traffic() if name == "uniform_u32_100M_radix_r8" else None,
                           "copy_ceiling_gbs": copy_gbs,
                           "frac_of_copy": (round(per_pass / (avg.get("pass", float("nan")) * 1e-3) / 1e9 / copy_gbs, 4)
@@ -438,33 +445,59 @@ def run_batched(name, p, args):
     steps = max(1, args.steps // 4)
     ms_stream = _timed(fn, steps, 1)
     avg = _kernel_avgs(ctx, fn, steps)
-    # the same calls recorded once into a HIP graph and replayed: one graph
-    # launch per batch
-    side = torch.cuda.Stream()
-    graph = I.capture(fn, side)
-    with torch.cuda.stream(side):
-        ms = _timed(lambda: graph.launch(side), steps, 1)
+    ms, launch = ms_stream, "one launch sequence per batch (no graph: profiling run)"
     steps_ms = list(_STEPS_MS)
-    graph_ok = bool(np.array_equal(out.cpu().numpy()[:1 << 20], np.concatenate(
-        [np.sort(keys[int(offsets[j]):int(offsets[j + 1])]) for j in range(len(offsets) - 1)])[:1 << 20]))
-    graph.close()
+    if not args.profile_light:
+        # the same calls recorded once into a HIP graph and replayed: one
+        # graph launch per batch
+        side = torch.cuda.Stream()
+        graph = I.capture(fn, side)
+        with torch.cuda.stream(side):
+            ms = _timed(lambda: graph.launch(side), steps, 1)
+        steps_ms = list(_STEPS_MS)
+        launch = "one HIP graph replay per batch"
+    # the first 2^20 outputs against numpy's sort of the arrays they come from
+    head, j = [], 0
+    while sum(a.size for a in head) < (1 << 20) and j < len(offsets) - 1:
+        head.append(np.sort(keys[int(offsets[j]):int(offsets[j + 1])]))
+        j += 1
+    ref = np.concatenate(head)[:1 << 20]
+    graph_ok = bool(np.array_equal(out[:ref.size].cpu().numpy(), ref))
+    if not args.profile_light:
+        graph.close()
     value = N / (ms * 1e-3) / 1e9
-    # the plain path: every array in its own buffer, one sort call each
-    arrs = [k[int(offsets[j]):int(offsets[j + 1])].clone() for j in range(len(offsets) - 1)]
-    outs = [torch.empty_like(a) for a in arrs]
+    ms_loop = None
+    if not args.profile_light:
+        # the plain path: every array in its own buffer, one sort call each
+        arrs = [k[int(offsets[j]):int(offsets[j + 1])].clone() for j in range(len(offsets) - 1)]
+        outs = [torch.empty_like(a) for a in arrs]
 
-    def loop():
-        for a, b in zip(arrs, outs):
-            I.sort(a, out=b)
-    ms_loop = _timed(loop, 1, 1)
+        def loop():
+            for a, b in zip(arrs, outs):
+                I.sort(a, out=b)
+        ms_loop = _timed(loop, 1, 1)
+        del arrs, outs
     _STEPS_MS[:] = steps_ms
-    roof = _roofline("k_onesweep<SegTiles> (one digit pass of the large arrays)", 2 * N * 4,
-                     avg.get("pass", float("nan")), {"kernel_avg_ms": {kk: round(x, 5) for kk, x in avg.items()}})
+    # what the pass launches move: the arrays longer than the LDS cutoff,
+    # each in the passes whose digit is not constant inside it (an array
+    # skips the others), averaged over the 4 pass launches of a sort
+    cut = int(choice.get("lds_cutoff") or SEG_LDS_MAX_U32)
+    moved = 0
+    for j in np.nonzero(np.diff(offsets) > cut)[0]:
+        seg = keys[int(offsets[j]):int(offsets[j + 1])]
+        diff = int(np.bitwise_or.reduce(seg ^ seg[0]))
+        moved += seg.size * sum(1 for p in range(4) if (diff >> (8 * p)) & 255)
+    roof = _roofline("k_onesweep<SegTiles> (one digit pass of the arrays above the LDS cutoff)", 2 * 4 * moved / 4,
+                     avg.get("pass", float("nan")), {"kernel_avg_ms": {kk: round(x, 5) for kk, x in avg.items()},
+                                                     "keys_moved_per_sort": int(moved)})
+    extra = {}
+    if ms_loop is not None:
+        extra = {"per_array_loop": {"value": round(N / (ms_loop * 1e-3) / 1e9, 3), "ms": round(ms_loop, 3)},
+                 "speedup_vs_per_array_loop": round(ms_loop / ms, 2)}
     return _line("Gkeys/s (batched segmented sort of 10,000 uint32 arrays)", value, "Gkeys/s", ms, steps, 1, "u32",
                  {"workload": name, "arrays": len(offsets) - 1, "keys": int(N), "sizes": "log-uniform [16, 2^20)",
-                  "tuned": choice, "tuned_in_this_run": tuned_now, "launch": "one HIP graph replay per batch"},
-                 roof, None, per_array_loop={"value": round(N / (ms_loop * 1e-3) / 1e9, 3), "ms": round(ms_loop, 3)},
-                 speedup_vs_per_array_loop=round(ms_loop / ms, 2),
+                  "tuned": choice, "tuned_in_this_run": tuned_now, "launch": launch},
+                 roof, None, **extra,
                  stream_launches={"value": round(N / (ms_stream * 1e-3) / 1e9, 3), "ms": round(ms_stream, 5)},
                  graph_output_matches_per_array_sort=graph_ok,
                  memory=_memory(4, False, int(N), len(offsets) - 1, **choice))
@@ -584,6 +617,13 @@ def main():
                     help="serving trace: output memory the requests in flight may hold")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB plain copy (for scaling hardware byte counters)")
+    ap.add_argument("--profile-light", action="store_true",
+                    help="batched workload: leave out the graph replay and the one-call-per-array comparison "
+                         "(for profiling runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline run: leave out the batched and serving results it appends")
+    ap.add_argument("--extras-serve-seconds", type=float, default=20.0,
+                    help="headline run: length of the serving trace whose results it appends")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -605,9 +645,51 @@ def main():
         fn = {"plain": run_plain, "pairs": run_pairs, "batched": run_batched, "serving": run_serving,
               "paper": run_paper}[kind]
         _STEPS_MS.clear()
-        print(json.dumps(fn(name, p, args)), flush=True)
+        line = fn(name, p, args)
         import torch
         torch.cuda.empty_cache()
+        if name == HEADLINE and len(names) == 1 and not args.no_extras:
+            line.update(headline_extras(args))
+        print(json.dumps(line), flush=True)
+        torch.cuda.empty_cache()
+
+
+def headline_extras(args):
+    """The metric's other halves, appended to the headline line: the batched
+    segmented sort of 10,000 arrays against one call per array, and the
+    serving loop (continuous batching against one request per launch) on a
+    shorter trace.  A failure is reported in the line, not raised."""
+    import copy
+
+    import torch
+    out = {}
+    steps_ms = list(_STEPS_MS)
+    try:
+        a = copy.copy(args)
+        a.steps = 8
+        r = run_batched("config4_batched_10k", {}, a)
+        out["config4_batched"] = {
+            "gkeys_per_s": r["value"], "ms_per_batch": r["ms_per_step"], "arrays": r["config"]["arrays"],
+            "keys": r["config"]["keys"], "tuned": r["config"]["tuned"],
+            "per_array_loop_gkeys_per_s": r["per_array_loop"]["value"],
+            "speedup_vs_per_array_loop": r["speedup_vs_per_array_loop"],
+            "output_matches_per_array_sort": r["graph_output_matches_per_array_sort"]}
+    except Exception as e:   # noqa: BLE001
+        out["config4_batched"] = {"error": f"{type(e).__name__}: {e}"}
+    torch.cuda.empty_cache()
+    try:
+        a = copy.copy(args)
+        a.serve_seconds = args.extras_serve_seconds
+        r = run_serving("config5_serving", {}, a)
+        sv = r["serving"]
+        out["config5_serving"] = {
+            "trace_seconds": a.serve_seconds, "rate_per_s": 2000,
+            "batched": sv["batched"], "plain": sv["plain"],
+            "checked_samples": sv.get("checked_samples"), "sample_mismatches": sv.get("sample_mismatches")}
+    except Exception as e:   # noqa: BLE001
+        out["config5_serving"] = {"error": f"{type(e).__name__}: {e}"}
+    _STEPS_MS[:] = steps_ms
+    return out
 
 
 if __name__ == "__main__":
