@@ -4,7 +4,7 @@
 // every bucket with insertion sort, Algorithm 1) and the small-segment path of
 // the segmented sort.  Any stable sort gives the same bytes; here it is an LSD
 // radix sort over 8-bit digits whose passes never leave LDS: each pass ranks
-// the keys stably (wave_rank plus a scan over digits and waves) and reorders
+// the keys stably (wave_rank_atomic plus a scan over digits and waves) and reorders
 // them through LDS.  A digit that is the same for every key of the segment
 // leaves it unchanged, so its pass is skipped.
 #pragma once
@@ -101,16 +101,13 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
     constexpr int RADIX = 256;
     constexpr int PASSES = (int)sizeof(K);
     constexpr int DPT = RADIX > NT ? RADIX / NT : 1;
-    constexpr int STAGE_BYTES = (TILE * (int)sizeof(K) > WAVES * RADIX * 8) ? TILE * (int)sizeof(K)
-                                                                           : WAVES * RADIX * 8;
-    __shared__ alignas(16) unsigned char s_raw[STAGE_BYTES];
+    __shared__ alignas(16) unsigned char s_raw[TILE * sizeof(K)];
     __shared__ uint32_t s_vstage[PAIRS ? TILE : 1];
     __shared__ uint32_t s_wcnt[WAVES * RADIX];
     __shared__ uint32_t s_excl[RADIX];
     __shared__ uint32_t s_scan[WAVES + 1];
     __shared__ K s_diff[WAVES];
     K *s_stage = reinterpret_cast<K *>(s_raw);
-    uint64_t *s_bits = reinterpret_cast<uint64_t *>(s_raw);
 
     uint32_t seg;
     if (a.list) {
@@ -153,20 +150,16 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
     for (int w = 0; w < WAVES; w++) diff |= s_diff[w];
 
     uint32_t *wcnt = s_wcnt + wave * RADIX;
-    uint64_t *bits = s_bits + wave * RADIX;
     for (int p = 0; p < PASSES; p++) {
         const uint32_t shift = 8u * (uint32_t)p;
         if (((diff >> shift) & 0xffu) == 0) continue;   // the same for every workgroup thread
-        for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) {
-            s_wcnt[i] = 0;
-            s_bits[i] = 0;
-        }
+        for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
         __syncthreads();
         uint32_t rk[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
             const uint32_t d = lofs + j * WAVE < m ? digit_at<K>(k[j], shift, 0xffu) : 0xffu;
-            rk[j] = wave_rank<8>(d, wcnt, bits, lane);
+            rk[j] = wave_rank_atomic(d, wcnt);
         }
         __syncthreads();
         uint32_t tcnt[DPT];

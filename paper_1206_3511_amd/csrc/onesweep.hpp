@@ -311,56 +311,6 @@ struct DescTiles {
 // ---------------------------------------------------------------- ranking
 
 // Stable rank of one slot of a wave (64 keys, one per lane, in lane order)
-// among the keys the wave has ranked so far: the keys with the same digit in
-// earlier slots (the per-wave counter wcnt[d]) plus the lanes below with the
-// same digit in this slot.  Peers come from a per-wave LDS bitmap that every
-// lane ORs its bit into; a wave whose lanes all hold one digit skips it.  For
-// digits wider than 8 bits the bitmap is indexed by the low 8 bits and the
-// remaining bits are matched with ballots.
-template <int BITS>
-__device__ __forceinline__ uint32_t wave_rank(uint32_t d, uint32_t *wcnt, uint64_t *bits, uint32_t lane)
-{
-    const uint32_t d0 = first_lane_value(d);
-    // the active lanes, taken before any branch: a ballot inside a branch
-    // sees only the lanes that took it
-    const uint64_t act = ballot(true);
-    uint32_t r;
-    if (ballot(d != d0) == 0) {
-        const uint32_t c = wcnt[d0];
-        const uint32_t below = mbcnt(act);
-        r = c + below;
-        wave_sync();
-        if (below == 0) wcnt[d0] = c + popc64(act);
-        wave_sync();
-    } else {
-        const uint32_t h = BITS > 8 ? (d & 255u) : d;
-        // each half of the wave sets its bit in its own 32-bit half of the
-        // 64-bit peer mask (half the LDS bytes of a 64-bit OR)
-        atomicOr(reinterpret_cast<uint32_t *>(&bits[h]) + (lane >> 5), 1u << (lane & 31));
-        wave_sync();
-        uint64_t peers = __hip_atomic_load(&bits[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        if (BITS > 8) {
-#pragma unroll
-            for (int b = 8; b < BITS; b++) {
-                const bool on = (d >> b) & 1u;
-                const uint64_t bb = ballot(on);
-                peers &= on ? bb : ~bb;
-            }
-        }
-        const uint32_t below = mbcnt(peers);
-        const uint32_t c = wcnt[d];
-        r = c + below;
-        wave_sync();
-        if (below == 0) {
-            wcnt[d] = c + popc64(peers);
-            __hip_atomic_store(&bits[h], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        }
-        wave_sync();
-    }
-    return r;
-}
-
-// Stable rank of one slot of a wave (64 keys, one per lane, in lane order)
 // among the keys the wave has ranked so far, by one LDS atomic add per key on
 // the wave's counter of the key's digit: the lanes of one add instruction
 // that hit the same counter are served in lane order (intsort_create checks
