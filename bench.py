@@ -173,16 +173,13 @@ def measured_traffic():
 
 
 def calibrate_copy():
-    """One plain copy of known size for the counter calibration: sorting 2^28
-    equal keys skips every pass, so the only data movement is k_final_copy
-    reading and writing 1 GiB each."""
+    """One plain copy of known size for the counter calibration: torch's
+    device copy of a 1 GiB buffer, 1 GiB read and 1 GiB written."""
     import torch
-
-    from paper_1206_3511_amd import intsort as I
     z = torch.zeros(1 << 28, dtype=torch.uint32, device="cuda:0")
     o = torch.empty_like(z)
     for _ in range(2):
-        I.sort(z, out=o)
+        o.copy_(z)
     torch.cuda.synchronize()
     del z, o
     torch.cuda.empty_cache()

@@ -83,6 +83,7 @@ struct HistArgs {
     uint32_t *chunk_sums;  // [chunk][radix] first pass: digit counts of each chunk of tiles
     uint32_t num_tiles;    // tiles of the first pass (with tile_counts)
     uint32_t tiles_per_wg; // tiles per chunk (<= FIRST_PASS_TILES_PER_CHUNK): one workgroup each
+    uint32_t num_chunks;   // chunks (histogram workgroups) of the first pass
 };
 
 // PER_TILE: the first pass's digits are counted per tile (a.tile_counts set)
@@ -249,8 +250,13 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
 
 // Turns the digit counts into exclusive offsets (where the run of every digit
 // value starts in the output of its pass) and plans the passes: which run,
-// which buffer each reads and writes.  One workgroup; runs after the
-// histogram kernel, so every count is complete and visible.
+// which buffer each reads and writes.  The plan is the last workgroup's; with
+// a first pass whose tiles were counted by the histogram kernel, workgroup d
+// < radix also turns the chunk totals of first-pass digit d into where each
+// chunk's run of d starts (the digit's start plus its counts in the earlier
+// chunks), so that a tile's start is its chunk's plus its own offset inside
+// the chunk.  Runs after the histogram kernel, so every count is complete
+// and visible.
 template <typename K, int BITS>
 __global__ __launch_bounds__(HIST_THREADS) void k_digit_plan(HistArgs a)
 {
@@ -262,6 +268,31 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_plan(HistArgs a)
     const uint32_t tid = threadIdx.x;
     const uint32_t n = a.n;
 
+    if (blockIdx.x + 1 < gridDim.x) {
+        // chunk scan of first-pass digit d (the grid has radix + 1 workgroups
+        // only when RADIX <= HIST_THREADS)
+        const uint32_t d = blockIdx.x;
+        __shared__ uint32_t s_start;
+        uint32_t c = 0;
+        if (tid < (uint32_t)RADIX)
+            for (uint32_t cp = 0; cp < a.copies; cp++) c += a.hist[cp * (uint32_t)(PASSES * RADIX) + tid];
+        uint32_t total_unused;
+        const uint32_t ex = block_exclusive_scan<HIST_THREADS>(c, s_scan, &total_unused);
+        if (tid == d) s_start = ex;
+        __syncthreads();
+        const uint32_t chunks = a.num_chunks;
+        const uint32_t per = (chunks + HIST_THREADS - 1) / HIST_THREADS;
+        const uint32_t j0 = min(chunks, tid * per), j1 = min(chunks, j0 + per);
+        uint32_t sum = 0;
+        for (uint32_t j = j0; j < j1; j++) sum += a.chunk_sums[(uint64_t)j * RADIX + d];
+        uint32_t run = s_start + block_exclusive_scan<HIST_THREADS>(sum, s_scan, &total_unused);
+        for (uint32_t j = j0; j < j1; j++) {
+            const uint32_t v = a.chunk_sums[(uint64_t)j * RADIX + d];
+            a.chunk_sums[(uint64_t)j * RADIX + d] = run;
+            run += v;
+        }
+        return;
+    }
     if (tid < (uint32_t)MAX_PASSES) s_const[tid] = 0;
     __syncthreads();
     for (int p = 0; p < PASSES; p++) {
@@ -300,6 +331,13 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_plan(HistArgs a)
             act[p] = ((uint32_t)p < a.max_passes) && !(a.skip && s_const[p]);
             A += act[p];
         }
+        if (A == 0 && !in_place && a.max_passes > 0) {
+            // every digit is constant: the last allowed pass still runs (the
+            // identity permutation), so the keys land in the output without
+            // a copy and the host never needs to launch one
+            act[min((uint32_t)PASSES, a.max_passes) - 1] = 1;
+            A = 1;
+        }
         uint32_t q = 0, prev_dst = BUF_IN;
         for (int p = 0; p < PASSES; p++) {
             uint32_t *w = a.plan + p * PLAN_WORDS;
@@ -326,31 +364,6 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_plan(HistArgs a)
         }
         f[2] = BUF_OUT;
         f[3] = A;
-    }
-}
-
-// Where each chunk of tiles starts its run of every first-pass digit: for
-// digit d (one workgroup each), sums[j][d] becomes excl[d] + the counts of d
-// in chunks 0 .. j-1.  A tile's offset is then its chunk's plus its own
-// offset inside the chunk.  Runs after the plan; nothing to do when the first
-// pass is skipped.
-__global__ __launch_bounds__(256) void k_chunk_sums_scan(uint32_t *sums, const uint32_t *excl,
-                                                         const uint32_t *plan, uint32_t chunks, uint32_t radix)
-{
-    __shared__ uint32_t s_scan[256 / WAVE + 1];
-    if (plan[0] == 0) return;
-    const uint32_t d = blockIdx.x;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (chunks + 255) / 256;
-    const uint32_t j0 = min(chunks, tid * per), j1 = min(chunks, j0 + per);
-    uint32_t sum = 0;
-    for (uint32_t j = j0; j < j1; j++) sum += sums[(uint64_t)j * radix + d];
-    uint32_t total;
-    uint32_t run = excl[d] + block_exclusive_scan<256>(sum, s_scan, &total);
-    for (uint32_t j = j0; j < j1; j++) {
-        const uint32_t c = sums[(uint64_t)j * radix + d];
-        sums[(uint64_t)j * radix + d] = run;
-        run += c;
     }
 }
 
@@ -505,6 +518,7 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
         h.num_tiles = (uint32_t)L.num_tiles;
         h.tiles_per_wg = first_pass_tiles_per_chunk(L.num_tiles);
         blocks = first_pass_chunks(L.num_tiles);
+        h.num_chunks = (uint32_t)blocks;
     }
     bool launched = false;
     if constexpr (sizeof(K) == 4 && C::RADIX <= HIST_THREADS) {
@@ -519,10 +533,10 @@ static hipError_t launch_histogram(const RadixCall &c, uint32_t *hist, bool fina
                            s, static_cast<const K *>(c.keys_in), h);
     if (t) t->mark(INTSORT_KERNEL_DIGIT_HISTOGRAM, 0, s);
     if (finalize) {
-        hipLaunchKernelGGL((k_digit_plan<K, BITS>), dim3(1), dim3(HIST_THREADS), 0, s, h);
-        if (h.tile_counts)
-            hipLaunchKernelGGL(k_chunk_sums_scan, dim3((uint32_t)C::RADIX), dim3(256), 0, s, h.chunk_sums, h.excl,
-                               h.plan, (uint32_t)blocks, (uint32_t)C::RADIX);
+        // one workgroup plans; with per-tile first-pass counts, one more per
+        // digit scans the chunk totals
+        const uint32_t grid = h.tile_counts && C::RADIX <= HIST_THREADS ? (uint32_t)C::RADIX + 1 : 1u;
+        hipLaunchKernelGGL((k_digit_plan<K, BITS>), dim3(grid), dim3(HIST_THREADS), 0, s, h);
         if (t) t->mark(INTSORT_KERNEL_PLAN, 0, s);
     }
     return hipGetLastError();
@@ -597,11 +611,17 @@ static hipError_t run_typed(const RadixCall &c, hipStream_t s)
         if (c.timer) c.timer->mark(INTSORT_KERNEL_PASS, (uint32_t)p, s);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    uint64_t blocks = (c.n + 255) / 256;
-    const uint64_t cap = (uint64_t)current_cus() * 4;
-    if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL((k_plan_final_copy<K, PAIRS>), dim3((uint32_t)blocks), dim3(256), 0, s, a.in, a.out, a.tmp,
-                       a.vin, a.vout, a.vtmp, plan + MAX_PASSES * PLAN_WORDS, (uint32_t)c.n);
+    // Out of place with at least one pass allowed, the plan routes the last
+    // pass that runs (one always does) into the output, so nothing is left
+    // to copy; otherwise the plan's final-copy words say what moves
+    const bool in_place = c.keys_in == c.keys_out || (c.pairs && c.vals_in == c.vals_out);
+    if (in_place || c.max_passes <= 0) {
+        uint64_t blocks = (c.n + 255) / 256;
+        const uint64_t cap = (uint64_t)current_cus() * 4;
+        if (blocks > cap) blocks = cap;
+        hipLaunchKernelGGL((k_plan_final_copy<K, PAIRS>), dim3((uint32_t)blocks), dim3(256), 0, s, a.in, a.out,
+                           a.tmp, a.vin, a.vout, a.vtmp, plan + MAX_PASSES * PLAN_WORDS, (uint32_t)c.n);
+    }
     if (c.timer) c.timer->mark(INTSORT_KERNEL_COPY, 0, s);
     return hipGetLastError();
 }
