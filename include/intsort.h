@@ -44,7 +44,20 @@
 extern "C" {
 #endif
 
-typedef enum intsort_status {
+/*
+ * The enumerations below are passed as 32-bit unsigned integers: that is the
+ * type a C compiler gives them (no enumerator is negative), and C++ callers
+ * and the library see them with that fixed underlying type, so an
+ * out-of-range value from a C caller is an ordinary value there too, and is
+ * rejected with INTSORT_ERR_INVALID_ARGUMENT.
+ */
+#ifdef __cplusplus
+#define INTSORT_ENUM(name) enum name : uint32_t
+#else
+#define INTSORT_ENUM(name) enum name
+#endif
+
+typedef INTSORT_ENUM(intsort_status) {
     INTSORT_OK = 0,
     INTSORT_ERR_INVALID_ARGUMENT = 1, /* null pointer with n > 0, bad enum, overlap */
     INTSORT_ERR_MISALIGNED = 2,       /* a base pointer is not 16-byte aligned */
@@ -69,7 +82,7 @@ typedef enum intsort_status {
  *            finite positives < +inf < +NaN, NaNs ordered by their payload
  *            bits; keys with identical bits keep their input order.
  */
-typedef enum intsort_key_type {
+typedef INTSORT_ENUM(intsort_key_type) {
     INTSORT_U32 = 0,
     INTSORT_U64 = 1,
     INTSORT_I32 = 2,
@@ -78,7 +91,7 @@ typedef enum intsort_key_type {
     INTSORT_F64 = 5
 } intsort_key_type;
 
-typedef enum intsort_algo {
+typedef INTSORT_ENUM(intsort_algo) {
     INTSORT_RADIX_LSD = 0, /* Algorithm 4 over a stable per-digit counting sort */
     INTSORT_BUCKET = 1,    /* Algorithm 2: range, bucket scatter, per-bucket sort;
                               keys found already in nondecreasing order by the
@@ -200,7 +213,8 @@ void intsort_default_options(intsort_options *opts);
  * memory and waits for its kernel; a device that fails it is refused with
  * INTSORT_ERR_UNSUPPORTED.  The calling thread's current device is left as
  * it was.  *ctx receives the handle; destroy it with
- * intsort_destroy.  hip_device = -1 makes a planning context that touches no
+ * intsort_destroy (destroying NULL does nothing and returns INTSORT_OK).
+ * hip_device = -1 makes a planning context that touches no
  * device: workspace sizes and argument checks work on it, and a sort call
  * whose arguments pass the checks returns INTSORT_ERR_UNSUPPORTED.
  */
@@ -264,7 +278,8 @@ intsort_status intsort_sort_pairs(intsort_ctx *ctx, intsort_key_type kt, const v
  * d_offsets[num_segments] = n_total; empty segments allowed) and every
  * segment [d_offsets[s], d_offsets[s+1]) is sorted on its own; nothing moves
  * between segments.  The offsets live on the device and are not validated
- * on the host.  Segment starts need no alignment.
+ * on the host.  Segment starts need no alignment.  num_segments = 0 with
+ * n_total > 0 is INTSORT_ERR_INVALID_ARGUMENT (no segment holds the keys).
  */
 intsort_status intsort_segmented_sort_keys(intsort_ctx *ctx, intsort_key_type kt,
                                            const void *keys_in, void *keys_out, uint64_t n_total,
@@ -401,7 +416,7 @@ intsort_status intsort_graph_destroy(intsort_graph *graph);
  * before it and the event after it.  Then it forgets them.  Timing a context
  * from two threads at once is not supported.
  */
-typedef enum intsort_kernel_kind {
+typedef INTSORT_ENUM(intsort_kernel_kind) {
     INTSORT_KERNEL_INIT = 0,
     INTSORT_KERNEL_DIGIT_HISTOGRAM = 1,
     INTSORT_KERNEL_PASS = 2,

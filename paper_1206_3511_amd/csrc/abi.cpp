@@ -442,6 +442,7 @@ static intsort_status segmented_common(intsort_ctx *ctx, intsort_key_type kt, co
     intsort_options o;
     intsort_status st = read_opts(ctx, opts_in, kt, n_total, true, &o);
     if (st != INTSORT_OK) return st;
+    if (num_segments == 0 && n_total != 0) return INTSORT_ERR_INVALID_ARGUMENT;
     if (n_total == 0 || num_segments == 0) return INTSORT_OK;
     if (!d_offsets || !keys_in || !keys_out) return INTSORT_ERR_INVALID_ARGUMENT;
     if (pairs && (!vals_in || !vals_out)) return INTSORT_ERR_INVALID_ARGUMENT;
