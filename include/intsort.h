@@ -335,11 +335,20 @@ intsort_status intsort_batched_sort_keys(intsort_ctx *ctx, intsort_key_type kt,
  * submission.  max_batch = 1 with slots = 1 is the plain one-request-per-
  * launch path.
  *
+ * A batch whose launch fails (a HIP call returns an error) or whose
+ * completion event reports an error fails as a whole: each of its requests
+ * finishes as failed, after whatever part of the batch was enqueued has
+ * finished, and the worker goes on with the next batch.
+ *
  * intsort_server_poll: *done = 1 and INTSORT_OK when finished,
- *   INTSORT_ERR_NOT_READY while waiting or running.
+ *   INTSORT_ERR_NOT_READY while waiting or running, *done = 1 and
+ *   INTSORT_ERR_HIP when the request failed.
  * intsort_server_completed: tickets (and latencies) finished since the last
- *   call, oldest first, at most `capacity`; finished tickets are forgotten.
- * intsort_server_drain: blocks until every submitted request has finished.
+ *   call, failed ones included, oldest first, at most `capacity`; returns
+ *   INTSORT_ERR_HIP when at least one listed ticket failed (poll tells which).
+ *   Finished tickets are forgotten, failed ones once poll has reported them.
+ * intsort_server_drain: blocks until every submitted request has finished;
+ *   INTSORT_ERR_HIP when a request failed since the previous drain.
  * intsort_server_destroy: drains, stops the worker, frees the workspaces.
  */
 typedef struct intsort_server intsort_server;
@@ -353,6 +362,14 @@ intsort_status intsort_server_completed(intsort_server *server, uint64_t *ticket
                                         uint32_t capacity, uint32_t *count);
 intsort_status intsort_server_drain(intsort_server *server);
 intsort_status intsort_server_destroy(intsort_server *server);
+
+/*
+ * For tests of the failure path (a fault-injection hook): the next `count`
+ * batch launches of the server's worker fail before anything is enqueued,
+ * as when the launch's first HIP call returns an error, so their requests
+ * finish as failed as described above.  count = 0 cancels what is left.
+ */
+intsort_status intsort_server_fail_next_launches(intsort_server *server, uint32_t count);
 
 /*
  * Step-level entry points.  Each runs one step of the sorts above on its own

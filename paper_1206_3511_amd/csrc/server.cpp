@@ -43,6 +43,7 @@ struct Req {
     uint64_t bytes;
     clk::time_point t_submit, t_done;
     int state;   // 0 waiting, 1 running, 2 done, 3 failed
+    bool listed, polled;   // a failed request is forgotten once both calls have reported it
 };
 
 struct Slot {
@@ -79,12 +80,29 @@ struct intsort_server {
     uint64_t next_ticket = 1;
     uint64_t outstanding = 0;     // submitted and not done
     bool stop = false;
-    int launch_error = 0;
+    uint64_t failed_since_drain = 0;   // requests that failed since the last intsort_server_drain
+    uint32_t inject_failures = 0;      // batch launches still to fail on purpose
     std::thread worker;
 
     void run();
     bool launch(Slot &slot, const std::vector<Req> &batch);
+    void finish(const std::vector<uint64_t> &tickets, bool ok);
 };
+
+// marks the requests of one batch finished (done or failed); called with the lock held
+void intsort_server::finish(const std::vector<uint64_t> &tickets, bool ok)
+{
+    const clk::time_point now = clk::now();
+    for (uint64_t t : tickets) {
+        Req &r = reqs.at(t);
+        r.state = ok ? 2 : 3;
+        r.t_done = now;
+        in_flight -= r.bytes;
+        completed.push_back(t);
+        outstanding--;
+        if (!ok) failed_since_drain++;
+    }
+}
 
 // runs without the lock: it sees only copies of the requests
 bool intsort_server::launch(Slot &slot, const std::vector<Req> &batch)
@@ -125,15 +143,7 @@ void intsort_server::run()
             if (!sl.busy) continue;
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
-            const clk::time_point now = clk::now();
-            for (uint64_t t : sl.tickets) {
-                Req &r = reqs.at(t);
-                r.state = q == hipSuccess ? 2 : 3;
-                r.t_done = now;
-                in_flight -= r.bytes;
-                completed.push_back(t);
-                outstanding--;
-            }
+            finish(sl.tickets, q == hipSuccess);
             sl.tickets.clear();
             sl.busy = false;
             progress = true;
@@ -163,20 +173,17 @@ void intsort_server::run()
             for (uint64_t t : batch) reqs.at(t).state = 1;
             sl.busy = true;
             sl.tickets = batch;
+            const bool inject = inject_failures > 0;
+            if (inject) inject_failures--;
             lk.unlock();
-            const bool ok = launch(sl, copies);
+            // an injected failure enqueues nothing, as when the first HIP call of the launch fails
+            const bool ok = !inject && launch(sl, copies);
+            // whatever part of a failed launch was enqueued finishes before the
+            // requests are reported, so their arrays are free when the caller hears
+            if (!ok) (void)hipStreamSynchronize(sl.stream);
             lk.lock();
             if (!ok) {
-                launch_error = 1;
-                const clk::time_point now = clk::now();
-                for (uint64_t t : batch) {
-                    Req &r = reqs.at(t);
-                    r.state = 3;
-                    r.t_done = now;
-                    in_flight -= r.bytes;
-                    completed.push_back(t);
-                    outstanding--;
-                }
+                finish(batch, false);
                 sl.tickets.clear();
                 sl.busy = false;
             }
@@ -284,11 +291,15 @@ intsort_status intsort_server_poll(intsort_server *s, uint64_t ticket, int *done
         std::lock_guard<std::mutex> g(s->mu);
         auto it = s->reqs.find(ticket);
         if (it == s->reqs.end()) return INTSORT_ERR_INVALID_ARGUMENT;
-        const Req &r = it->second;
+        Req &r = it->second;
         *done = r.state >= 2;
         if (latency_s)
             *latency_s = *done ? std::chrono::duration<double>(r.t_done - r.t_submit).count() : 0.0;
-        if (r.state == 3) return INTSORT_ERR_HIP;
+        if (r.state == 3) {
+            r.polled = true;
+            if (r.listed) s->reqs.erase(it);
+            return INTSORT_ERR_HIP;
+        }
         return *done ? INTSORT_OK : INTSORT_ERR_NOT_READY;
     } catch (...) {
         return INTSORT_ERR_INTERNAL;
@@ -303,16 +314,20 @@ intsort_status intsort_server_completed(intsort_server *s, uint64_t *tickets, do
         std::lock_guard<std::mutex> g(s->mu);
         uint32_t m = 0;
         size_t i = 0;
+        bool failed = false;
         for (; i < s->completed.size() && m < capacity; i++, m++) {
             const uint64_t t = s->completed[i];
             Req &r = s->reqs.at(t);
             tickets[m] = t;
             if (latency_s) latency_s[m] = std::chrono::duration<double>(r.t_done - r.t_submit).count();
-            if (r.state == 2) s->reqs.erase(t);   // failed requests stay visible to poll
+            // a failed request stays visible to poll until poll has reported it
+            r.listed = true;
+            if (r.state == 3) failed = true;
+            if (r.state == 2 || r.polled) s->reqs.erase(t);
         }
         s->completed.erase(s->completed.begin(), s->completed.begin() + (long)i);
         *count = m;
-        return s->launch_error ? INTSORT_ERR_HIP : INTSORT_OK;
+        return failed ? INTSORT_ERR_HIP : INTSORT_OK;
     } catch (...) {
         return INTSORT_ERR_INTERNAL;
     }
@@ -325,7 +340,21 @@ intsort_status intsort_server_drain(intsort_server *s)
         std::unique_lock<std::mutex> lk(s->mu);
         s->cv.notify_one();
         s->idle.wait(lk, [s] { return s->outstanding == 0; });
-        return s->launch_error ? INTSORT_ERR_HIP : INTSORT_OK;
+        const bool failed = s->failed_since_drain > 0;
+        s->failed_since_drain = 0;
+        return failed ? INTSORT_ERR_HIP : INTSORT_OK;
+    } catch (...) {
+        return INTSORT_ERR_INTERNAL;
+    }
+}
+
+intsort_status intsort_server_fail_next_launches(intsort_server *s, uint32_t count)
+{
+    try {
+        if (!s) return INTSORT_ERR_INVALID_ARGUMENT;
+        std::lock_guard<std::mutex> g(s->mu);
+        s->inject_failures = count;
+        return INTSORT_OK;
     } catch (...) {
         return INTSORT_ERR_INTERNAL;
     }

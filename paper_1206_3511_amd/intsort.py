@@ -39,7 +39,7 @@ EXPORTED = (
     "intsort_minmax", "intsort_bucket_histogram", "intsort_read_device_error",
     "intsort_timing_enable", "intsort_timing_read", "intsort_batched_sort_keys",
     "intsort_server_create", "intsort_server_submit", "intsort_server_poll", "intsort_server_completed",
-    "intsort_server_drain", "intsort_server_destroy",
+    "intsort_server_drain", "intsort_server_destroy", "intsort_server_fail_next_launches",
     "intsort_capture_begin", "intsort_capture_end", "intsort_graph_launch", "intsort_graph_destroy",
     "intsort_load_tuning", "intsort_device_key",
 )
@@ -121,6 +121,7 @@ def lib():
                                                ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
         L.intsort_server_drain.argtypes = [_vp]
         L.intsort_server_destroy.argtypes = [_vp]
+        L.intsort_server_fail_next_launches.argtypes = [_vp, ctypes.c_uint32]
         L.intsort_load_tuning.argtypes = [_vp, ctypes.c_char_p]
         L.intsort_device_key.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
         L.intsort_timing_enable.argtypes = [_vp, _i]
@@ -474,9 +475,21 @@ def capture(fn, stream, device: int = 0) -> Graph:
     return Graph(g, device, keep=[ctx._ws.get(stream.cuda_stream)])
 
 
+class ServerRequestsFailed(IntsortError):
+    """Some requests listed by Server.completed failed (their batch's launch
+    or completion reported a HIP error).  `tickets` are the failed ones,
+    `results` everything that call listed, failed ones included."""
+
+    def __init__(self, tickets, results):
+        self.tickets = tickets
+        self.results = results
+        super().__init__(ERR_HIP, f"intsort_server_completed (failed tickets {tickets})")
+
+
 class Server:
     """Continuous-batching sort server (intsort_server_*).  Keeps every
-    submitted request's tensors alive until it completes."""
+    submitted request's tensors alive until it completes.  `failed` holds the
+    tickets that completed() has seen fail."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 64 << 30, max_batch: int = 64, slots: int = 2):
         torch.cuda.set_device(device)
@@ -484,6 +497,7 @@ class Server:
         _check(lib().intsort_server_create(context(device).handle, budget_bytes, max_batch, slots,
                                            ctypes.byref(self.handle)), "intsort_server_create")
         self._live: dict[int, tuple] = {}
+        self.failed: set[int] = set()
         self._buf_t = (_u64 * 4096)()
         self._buf_l = (ctypes.c_double * 4096)()
 
@@ -496,18 +510,35 @@ class Server:
         self._live[t.value] = (keys, out)
         return t.value
 
-    def completed(self) -> list[tuple[int, float]]:
-        """(ticket, latency seconds) of requests finished since the last call."""
-        res = []
+    def completed(self, raise_on_failure: bool = True) -> list[tuple[int, float]]:
+        """(ticket, latency seconds) of requests finished since the last call,
+        failed ones included.  Failed tickets go into `failed`; with
+        raise_on_failure the call then raises ServerRequestsFailed."""
+        res, bad = [], []
         while True:
             cnt = ctypes.c_uint32(0)
-            _check(lib().intsort_server_completed(self.handle, self._buf_t, self._buf_l, 4096, ctypes.byref(cnt)),
-                   "intsort_server_completed")
+            rc = lib().intsort_server_completed(self.handle, self._buf_t, self._buf_l, 4096, ctypes.byref(cnt))
+            if rc not in (OK, ERR_HIP):
+                raise IntsortError(rc, "intsort_server_completed")
             for i in range(cnt.value):
-                res.append((int(self._buf_t[i]), float(self._buf_l[i])))
-                self._live.pop(int(self._buf_t[i]), None)
+                t = int(self._buf_t[i])
+                res.append((t, float(self._buf_l[i])))
+                self._live.pop(t, None)
+                if rc == ERR_HIP:
+                    done = ctypes.c_int(0)
+                    if lib().intsort_server_poll(self.handle, t, ctypes.byref(done), None) == ERR_HIP:
+                        bad.append(t)
             if cnt.value < 4096:
-                return res
+                break
+        self.failed.update(bad)
+        if bad and raise_on_failure:
+            raise ServerRequestsFailed(bad, res)
+        return res
+
+    def fail_next_launches(self, count: int):
+        """Makes the next `count` batch launches fail before anything is
+        enqueued (a test hook for the failure path)."""
+        _check(lib().intsort_server_fail_next_launches(self.handle, count), "intsort_server_fail_next_launches")
 
     def poll(self, ticket: int):
         done = ctypes.c_int(0)

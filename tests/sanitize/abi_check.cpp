@@ -117,6 +117,7 @@ int main(int argc, char **argv)
     CHECK(intsort_server_create(ctx, 1u << 30, 0, 2, &srv) == INTSORT_ERR_INVALID_ARGUMENT);
     CHECK(intsort_server_submit(nullptr, INTSORT_U32, p, p, 1, nullptr) == INTSORT_ERR_INVALID_ARGUMENT);
     CHECK(intsort_server_destroy(nullptr) == INTSORT_ERR_INVALID_ARGUMENT);
+    CHECK(intsort_server_fail_next_launches(nullptr, 1) == INTSORT_ERR_INVALID_ARGUMENT);
     CHECK(intsort_capture_begin(ctx, nullptr) != INTSORT_OK);
     CHECK(intsort_timing_enable(ctx, 1) != INTSORT_OK || true);
     CHECK(intsort_destroy(ctx) == INTSORT_OK);

@@ -91,3 +91,59 @@ def test_server_rejects_over_budget():
         srv.submit(a, torch.empty_like(a))
     assert e.value.status == I.ERR_OVER_BUDGET
     srv.close()
+
+
+def test_server_failed_launch_reports_and_keeps_serving():
+    """A batch whose launch fails finishes its requests as failed (poll and
+    completed report INTSORT_ERR_HIP, drain reports it once) and the server
+    goes on serving: later requests equal the oracle's sort."""
+    # one key type: max_batch bounds the arrays of each key type in a batch
+    reqs = [workloads.config2_keys(i % 7, n, 9000 + i).astype(np.uint32)
+            for i, n in enumerate([3000, 40_000, 1, 17_000] * 2)]
+    ins = [dev(a) for a in reqs]
+    outs = [torch.zeros_like(t) for t in ins]
+    torch.cuda.synchronize()
+    # plain path: one request per launch, in arrival order, so the first
+    # two launches carry the first two requests
+    srv = I.Server(0, budget_bytes=64 << 30, max_batch=1, slots=1)
+    srv.fail_next_launches(2)
+    tickets = [srv.submit(a, b) for a, b in zip(ins[:5], outs[:5])]
+    with pytest.raises(I.IntsortError) as e:
+        srv.drain()
+    assert e.value.status == I.ERR_HIP
+    srv.drain()                                  # reported once: the next drain is clean
+    with pytest.raises(I.ServerRequestsFailed) as e:
+        srv.completed()
+    assert sorted(e.value.tickets) == tickets[:2]
+    assert sorted(t for t, _ in e.value.results) == tickets
+    assert srv.failed == set(tickets[:2])
+    for t in tickets[:2]:                        # forgotten once poll and completed reported them
+        with pytest.raises(I.IntsortError) as e:
+            srv.poll(t)
+        assert e.value.status == I.ERR_INVALID_ARGUMENT
+    for o in outs[:2]:                           # an injected failure enqueues nothing
+        assert not host(o).any()
+    for a, o in zip(reqs[2:5], outs[2:5]):
+        np.testing.assert_array_equal(host(o), oracle.radix_lsd(a).keys)
+    # the server keeps serving: nothing else fails
+    more = [srv.submit(a, b) for a, b in zip(ins[5:], outs[5:])]
+    srv.drain()
+    assert sorted(t for t, _ in srv.completed()) == more
+    for a, o in zip(reqs[5:], outs[5:]):
+        np.testing.assert_array_equal(host(o), oracle.radix_lsd(a).keys)
+    # a failure while batching fails whole batches, never a request that ran
+    srv.close()
+    srv = I.Server(0, budget_bytes=64 << 30, max_batch=8, slots=2)
+    srv.fail_next_launches(1)
+    outs = [torch.zeros_like(t) for t in ins]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(a, b) for a, b in zip(ins, outs)]
+    with pytest.raises(I.IntsortError):
+        srv.drain()
+    done = srv.completed(raise_on_failure=False)
+    assert sorted(t for t, _ in done) == tickets
+    assert 1 <= len(srv.failed) <= 8
+    for t, a, o in zip(tickets, reqs, outs):
+        if t not in srv.failed:
+            np.testing.assert_array_equal(host(o), oracle.radix_lsd(a).keys)
+    srv.close()
