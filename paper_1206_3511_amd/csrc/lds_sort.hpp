@@ -150,14 +150,23 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
     for (int w = 0; w < WAVES; w++) diff |= s_diff[w];
 
     uint32_t *wcnt = s_wcnt + wave * RADIX;
-    for (int p = 0; p < PASSES; p++) {
-        const uint32_t shift = 8u * (uint32_t)p;
-        if (((diff >> shift) & 0xffu) == 0) continue;   // the same for every workgroup thread
+    // slot j of this wave holds keys (index < m) or only padding; slots of
+    // padding alone are neither ranked nor placed (the ranked slots are the
+    // first ceil(m / 64) of the segment, so the placed keys take positions
+    // 0 .. 64 ceil(m / 64) - 1, the real ones 0 .. m - 1)
+    const uint32_t wbase = __builtin_amdgcn_readfirstlane(wave * (uint32_t)(IPT * WAVE));
+    auto live = [&](int j) { return wbase + (uint32_t)(j * WAVE) < m; };
+
+    // One stable counting pass on bits shift .. shift+7: every key's new
+    // position goes to LDS (s_stage, s_vstage).
+    auto rank_place = [&](uint32_t shift) {
         for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
         __syncthreads();
         uint32_t rk[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
+            rk[j] = 0;
+            if (!live(j)) continue;
             const uint32_t d = lofs + j * WAVE < m ? digit_at<K>(k[j], shift, 0xffu) : 0xffu;
             rk[j] = wave_rank_atomic(d, wcnt);
         }
@@ -191,20 +200,31 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
+            if (!live(j)) continue;
             const uint32_t d = lofs + j * WAVE < m ? digit_at<K>(k[j], shift, 0xffu) : 0xffu;
             const uint32_t pos = s_excl[d] + s_wcnt[wave * RADIX + d] + rk[j];
             s_stage[pos] = k[j];
             if (PAIRS) s_vstage[pos] = v[j];
         }
         __syncthreads();
-        // padding keys took the largest digit and the last positions, so
-        // the first m positions hold the segment in its new order
+    };
+    // padding keys took the largest digit and the last positions, so the
+    // first m positions hold the segment in its new order
+    auto read_back = [&]() {
 #pragma unroll
         for (int j = 0; j < IPT; j++) {
+            if (!live(j)) continue;
             k[j] = s_stage[lofs + j * WAVE];
             if (PAIRS) v[j] = s_vstage[lofs + j * WAVE];
         }
         __syncthreads();
+    };
+
+    for (int p = 0; p < PASSES; p++) {
+        const uint32_t shift = 8u * (uint32_t)p;
+        if (((diff >> shift) & 0xffu) == 0) continue;   // the same for every workgroup thread
+        rank_place(shift);
+        read_back();
     }
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
