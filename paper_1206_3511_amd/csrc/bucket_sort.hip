@@ -184,17 +184,22 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
 
 // After the scatter the keys are grouped by bucket, in bucket order, so
 // bucket b starts at the first position whose bucket is at least b (an empty
-// bucket where the next nonempty one does, offsets[B] = n).  Position p
-// therefore starts buckets b(p-1)+1 .. b(p), reading b(-1) as -1 and b(n)
-// as B, and every offset has exactly one such position.  The runs of the 64
-// positions of a wave are adjacent, so the wave writes them together: lane t
-// takes the t-th offset of the runs, finds its position by a binary search
-// over the runs' running lengths, and the stores of a wave are contiguous.
-// A run longer than START_RUN (a wide gap of empty buckets) is cut into
-// pieces of START_RUN and listed for k_bucket_start_runs instead.
+// bucket where the next nonempty one does, offsets[B] = n).  With
+// c(p) = b(p) + 1, c(-1) = 0 and c(n) = B + 1, position p therefore starts
+// buckets c(p-1) .. c(p)-1, and every offset has exactly one such position.
+// A lane takes BS_V consecutive positions (vector loads), a wave 64 BS_V; a
+// wave whose positions start no bucket (most of them when B is much smaller
+// than n) writes nothing.  Otherwise the runs of its positions are adjacent,
+// in position order, so the wave writes them together: lane t takes the t-th
+// offset of the runs, finds its position by a binary search over the runs'
+// running lengths, and the stores of a wave are contiguous.  A run longer
+// than START_RUN (a wide gap of empty buckets) is cut into pieces of
+// START_RUN and listed for k_bucket_start_runs instead.
 constexpr uint64_t START_RUN = 1024;
 constexpr int CTR_START_RUNS = 48;   // counter word: pieces listed
 static_assert(CTR_START_RUNS < CTR_WORDS && CTR_START_RUNS > CTR_ERROR, "a free counter word");
+constexpr int BS_V = 8;                 // positions per lane
+constexpr int BS_WP = WAVE * BS_V;      // positions per wave and step
 
 struct StartRun {
     uint64_t lo, hi, p;   // offsets[lo .. hi) = p
@@ -214,55 +219,84 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_starts(const K *__restric
                                                               uint32_t *counters, uint64_t run_cap,
                                                               const uint64_t *skip)
 {
-    __shared__ uint32_t s_incl[BK_THREADS];
-    __shared__ uint64_t s_lo[BK_THREADS], s_p[BK_THREADS];
+    constexpr int NW = BK_THREADS / WAVE;
+    __shared__ uint32_t s_excl[NW][BS_WP + 1];   // running run length before each position
+    __shared__ uint64_t s_lo[NW][BS_WP];         // first offset of each position's run
     if (*skip) return;   // keys already sorted: no bucket starts needed
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
     const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
-    uint32_t *w_incl = s_incl + wave * WAVE;
-    uint64_t *w_lo = s_lo + wave * WAVE, *w_p = s_p + wave * WAVE;
-    const uint64_t stride = (uint64_t)gridDim.x * BK_THREADS;
+    uint32_t *w_excl = s_excl[wave];
+    uint64_t *w_lo = s_lo[wave];
+    const uint64_t end = (uint64_t)B + 1;   // c(n), and c of every position past n
+    const uint64_t stride = (uint64_t)gridDim.x * NW * BS_WP;
     // the same trip count for every lane of a wave
-    for (uint64_t base = (uint64_t)blockIdx.x * BK_THREADS + wave * WAVE; base <= n; base += stride) {
-        const uint64_t p = base + lane;
-        uint64_t lo = 0, hi = 0;
-        if (p <= n) {
-            lo = p == 0 ? 0 : (uint64_t)bucket_of(m, keys[p - 1]) + 1;
-            hi = p == n ? (uint64_t)B + 1 : (uint64_t)bucket_of(m, keys[p]) + 1;   // exclusive
-        }
-        uint32_t len = 0;
-        if (hi < lo) {   // not grouped by bucket: cannot happen after the scatter
-            atomicOr(&counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
-        } else if (hi - lo <= START_RUN) {
-            len = (uint32_t)(hi - lo);
+    for (uint64_t base = ((uint64_t)blockIdx.x * NW + wave) * BS_WP; base <= n; base += stride) {
+        const uint64_t p0 = base + (uint64_t)lane * BS_V;
+        uint64_t c[BS_V];
+        if (p0 + BS_V <= n) {
+            // whole vectors (p0 is a multiple of 8, the buffer 16-byte aligned)
+            constexpr int NV = BS_V * (int)sizeof(K) / 16;
+            const uint4 *vp = reinterpret_cast<const uint4 *>(keys + p0);
+            uint4 w[NV];
+#pragma unroll
+            for (int q = 0; q < NV; q++) w[q] = vp[q];
+            K key[BS_V];
+            __builtin_memcpy(key, w, sizeof(key));
+#pragma unroll
+            for (int i = 0; i < BS_V; i++) c[i] = (uint64_t)bucket_of(m, key[i]) + 1;
         } else {
-            const uint64_t pieces = (hi - lo + START_RUN - 1) / START_RUN;
-            const uint64_t at = atomicAdd(&counters[CTR_START_RUNS], (uint32_t)pieces);
-            for (uint64_t q = 0; q < pieces; q++) {
-                if (at + q >= run_cap) {   // sized so that this cannot happen
-                    atomicOr(&counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
-                    break;
-                }
-                const uint64_t a = lo + q * START_RUN;
-                runs[at + q] = StartRun{a, min(hi, a + START_RUN), p};
-            }
+#pragma unroll
+            for (int i = 0; i < BS_V; i++) c[i] = p0 + i < n ? (uint64_t)bucket_of(m, keys[p0 + i]) + 1 : end;
         }
-        const uint32_t incl = wave_inclusive_scan(len);
+        // c of the position before the lane's first one
+        uint64_t cprev = __shfl_up(c[BS_V - 1], 1, WAVE);
+        if (lane == 0) cprev = p0 == 0 ? 0 : (p0 - 1 < n ? (uint64_t)bucket_of(m, keys[p0 - 1]) + 1 : end);
+        uint32_t len[BS_V];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < BS_V; i++) {
+            const uint64_t lo = i == 0 ? cprev : c[i - 1], hi = c[i];
+            len[i] = 0;
+            if (hi < lo) {   // not grouped by bucket: cannot happen after the scatter
+                atomicOr(&counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
+            } else if (hi - lo <= START_RUN) {
+                len[i] = (uint32_t)(hi - lo);
+            } else {
+                const uint64_t pieces = (hi - lo + START_RUN - 1) / START_RUN;
+                const uint64_t at = atomicAdd(&counters[CTR_START_RUNS], (uint32_t)pieces);
+                for (uint64_t q = 0; q < pieces; q++) {
+                    if (at + q >= run_cap) {   // sized so that this cannot happen
+                        atomicOr(&counters[CTR_ERROR], DEVERR_SCATTER_RANGE);
+                        break;
+                    }
+                    const uint64_t a = lo + q * START_RUN;
+                    runs[at + q] = StartRun{a, min(hi, a + START_RUN), p0 + i};
+                }
+            }
+            mine += len[i];
+        }
+        if (ballot(mine != 0) == 0) continue;   // no bucket starts here
+        const uint32_t incl = wave_inclusive_scan(mine);
         const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-        w_incl[lane] = incl;
-        w_lo[lane] = lo;
-        w_p[lane] = p;
+        uint32_t run = incl - mine;
+#pragma unroll
+        for (int i = 0; i < BS_V; i++) {
+            w_excl[lane * BS_V + i] = run;
+            w_lo[lane * BS_V + i] = i == 0 ? cprev : c[i - 1];
+            run += len[i];
+        }
+        if (lane == WAVE - 1) w_excl[BS_WP] = total;
         wave_sync();
         for (uint32_t u = lane; u < total; u += WAVE) {
-            // the first lane whose runs end after offset u owns it
-            uint32_t x = 0, y = WAVE - 1;
+            // the last position whose runs start at or before offset u owns
+            // it (a position with an empty run shares its start with the next)
+            uint32_t x = 0, y = BS_WP - 1;
             while (x < y) {
-                const uint32_t mid = (x + y) / 2;
-                if (w_incl[mid] > u) y = mid;
-                else x = mid + 1;
+                const uint32_t mid = (x + y + 1) / 2;
+                if (w_excl[mid] <= u) x = mid;
+                else y = mid - 1;
             }
-            const uint32_t before = x > 0 ? w_incl[x - 1] : 0u;
-            offsets[w_lo[x] + (u - before)] = w_p[x];
+            offsets[w_lo[x] + (u - w_excl[x])] = base + x;
         }
         wave_sync();
     }
@@ -508,7 +542,8 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     if (!full_hist) {
         StartRun *runs = reinterpret_cast<StartRun *>(ws + L.runs);
         const uint64_t cap = start_run_cap(B);
-        uint64_t blocks = std::min<uint64_t>((c.n + 1 + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
+        const uint64_t per_block = (uint64_t)BK_THREADS * BS_V;
+        uint64_t blocks = std::min<uint64_t>((c.n + 1 + per_block - 1) / per_block, (uint64_t)fill_grid * 2);
         hipLaunchKernelGGL((k_bucket_starts<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
                            s, tmpb, c.n, minmax, B, offsets, runs, counters, cap, (const uint64_t *)sorted);
         hipLaunchKernelGGL(k_bucket_start_runs, dim3((uint32_t)std::min<uint64_t>(cap, (uint64_t)fill_grid * 4)),
