@@ -108,7 +108,16 @@ struct BucketPlanArgs {
     const uint64_t *skip;     // nonzero: the keys are already sorted, no pass runs
     uint32_t in_place;        // the passes write the caller's output, which aliases its
                               // input (keys or values): start in the scratch buffer
+    const uint64_t *minmax;
+    uint64_t *bucket_skip;    // set here: what the per-bucket sorts do (BSKIP_*)
 };
+
+// the per-bucket stage after the scatter: BSKIP_NONE sorts every bucket;
+// BSKIP_SORTED does nothing (the input was already in order and is copied);
+// BSKIP_SINGLE does nothing either, because B >= R: then b(k) is strictly
+// increasing in k, every bucket holds copies of one key value, and the
+// scattered keys are already the sorted output (they are copied there)
+constexpr uint64_t BSKIP_NONE = 0, BSKIP_SORTED = 1, BSKIP_SINGLE = 2;
 
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
 {
@@ -116,6 +125,10 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
     __shared__ uint32_t s_byte[2 * 256];
     const uint32_t tid = threadIdx.x;
     uint32_t *f = a.plan + MAX_PASSES * PLAN_WORDS;   // final-copy words
+    if (tid == 0) {
+        const uint64_t range_m1 = a.minmax[1] - a.minmax[0];   // R - 1
+        *a.bucket_skip = *a.skip ? BSKIP_SORTED : (range_m1 < (uint64_t)a.B ? BSKIP_SINGLE : BSKIP_NONE);
+    }
     if (*a.skip) {
         if (tid == 0) {
             for (uint32_t q = 0; q < a.passes; q++) a.plan[q * PLAN_WORDS] = 0;
@@ -324,6 +337,21 @@ __global__ void k_set_range(uint64_t *minmax, uint64_t lo, uint64_t hi, uint64_t
     *sorted = 1;
 }
 
+// With one key value per bucket the scattered keys (and values) are the
+// sorted output
+template <typename K>
+__global__ __launch_bounds__(BK_THREADS) void k_copy_if_single(const uint64_t *bucket_skip, const K *__restrict__ kin,
+                                                               K *__restrict__ kout, const uint32_t *__restrict__ vin,
+                                                               uint32_t *__restrict__ vout, uint64_t n)
+{
+    if (*bucket_skip != BSKIP_SINGLE) return;
+    const uint64_t stride = (uint64_t)gridDim.x * BK_THREADS;
+    for (uint64_t i = (uint64_t)blockIdx.x * BK_THREADS + threadIdx.x; i < n; i += stride) {
+        kout[i] = kin[i];
+        if (vout) vout[i] = vin[i];
+    }
+}
+
 // When the keys were already in order, the sort is the identity: the
 // output is a copy of the input (the stages before left it untouched)
 template <typename K>
@@ -417,7 +445,7 @@ BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_
     auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
     L.counters = take((size_t)CTR_WORDS * 4);
     L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
-    L.minmax = take(24);   // min, max, and whether the keys are already sorted
+    L.minmax = take(32);   // min, max, whether the keys are already sorted, the per-bucket stage
     L.counts = take(L.buckets <= BUCKET_LDS_HIST_MAX ? (size_t)L.buckets * 4 : 0);
     L.subhist = take((size_t)SUBHIST_WORDS * 4);
     L.excl = take((size_t)L.scatter_passes * radix * 4);
@@ -447,6 +475,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     uint32_t *plan = reinterpret_cast<uint32_t *>(ws + L.plan);
     uint64_t *minmax = reinterpret_cast<uint64_t *>(ws + L.minmax);
     uint64_t *sorted = minmax + 2;
+    uint64_t *bskip = minmax + 3;
     uint32_t *counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     uint32_t *subhist = reinterpret_cast<uint32_t *>(ws + L.subhist);
     uint32_t *excl = reinterpret_cast<uint32_t *>(ws + L.excl);
@@ -501,7 +530,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     // scatters into its own buffers)
     const bool alias = c.keys_in == c.keys_out || (PAIRS && c.vals_in == c.vals_out);
     BucketPlanArgs pa{counts, subhist, excl, offsets, plan, B, (uint32_t)C::RADIX, L.scatter_passes,
-                      full_hist ? 1u : 0u, c.n, sorted, scatter_only && alias ? 1u : 0u};
+                      full_hist ? 1u : 0u, c.n, sorted, scatter_only && alias ? 1u : 0u, minmax, bskip};
     hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(BK_THREADS), 0, s, pa);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(fill_grid), dim3(256), 0, s, status0,
                        (uint64_t)L.num_tiles * C::RADIX, 0u);
@@ -545,9 +574,9 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
         const uint64_t per_block = (uint64_t)BK_THREADS * BS_V;
         uint64_t blocks = std::min<uint64_t>((c.n + 1 + per_block - 1) / per_block, (uint64_t)fill_grid * 2);
         hipLaunchKernelGGL((k_bucket_starts<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
-                           s, tmpb, c.n, minmax, B, offsets, runs, counters, cap, (const uint64_t *)sorted);
+                           s, tmpb, c.n, minmax, B, offsets, runs, counters, cap, (const uint64_t *)bskip);
         hipLaunchKernelGGL(k_bucket_start_runs, dim3((uint32_t)std::min<uint64_t>(cap, (uint64_t)fill_grid * 4)),
-                           dim3(BK_THREADS), 0, s, runs, counters, cap, offsets, (const uint64_t *)sorted);
+                           dim3(BK_THREADS), 0, s, runs, counters, cap, offsets, (const uint64_t *)bskip);
         if (tm) tm->mark(INTSORT_KERNEL_PLAN, 1, s);
     }
 
@@ -561,7 +590,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     if (windows) {
         LdsSortArgs<WindowSrc<K>> la{};
         la.src = WindowSrc<K>{tmpb, static_cast<K *>(c.keys_out), PAIRS ? tmpb_v : nullptr,
-                              PAIRS ? c.vals_out : nullptr, offsets, minmax, B, HALF, c.n, sorted};
+                              PAIRS ? c.vals_out : nullptr, offsets, minmax, B, HALF, c.n, bskip};
         la.list = nullptr;
         la.direct_count = (uint32_t)((c.n + HALF - 1) / HALF);
         hipLaunchKernelGGL((k_lds_sort<K, PAIRS, 512, CL::LDS_MAX / 512, WindowSrc<K>>), dim3(la.direct_count),
@@ -586,8 +615,14 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     sc.ws = segws;
     sc.timer = tm;
     sc.min_size = windows ? HALF : 0u;   // the windows took these
-    sc.skip = sorted;
+    sc.skip = bskip;
     if ((e = segmented_sort_run(sc, s)) != hipSuccess) return e;
+    {
+        const uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
+        hipLaunchKernelGGL((k_copy_if_single<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
+                           s, (const uint64_t *)bskip, (const K *)tmpb, static_cast<K *>(c.keys_out),
+                           PAIRS ? (const uint32_t *)tmpb_v : nullptr, PAIRS ? c.vals_out : nullptr, c.n);
+    }
     copy_if_sorted();
     return hipGetLastError();
 }

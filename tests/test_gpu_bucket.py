@@ -257,3 +257,30 @@ def test_bucket_starts_with_wide_gaps(dtype, case):
     np.testing.assert_array_equal(host(ok), ref.keys)
     np.testing.assert_array_equal(host(ov), ref.vals)
     assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("span,B", [(4999, 5000), (5000, 5000), (5000, 4999), (200_000, 65536), (60_000, 65536),
+                                    (3000, 1 << 20)])
+@pytest.mark.parametrize("in_place", [False, True])
+def test_one_value_per_bucket(dtype, span, B, in_place):
+    """B >= R makes b(k) strictly increasing, so every bucket holds copies of
+    one key value and the per-bucket sorts are skipped; B one below R (and
+    B well below R) takes the usual path.  Both equal the oracle."""
+    n = 300_007
+    rng = np.random.default_rng(span + B)
+    base = 7 if dtype == np.uint32 else (1 << 40) + 3
+    keys = (rng.integers(0, span, n) + base).astype(dtype)
+    keys[:2] = [base, base + span - 1]   # R = span exactly
+    vals = np.arange(n, dtype=np.uint32)
+    kd, vd = dev(keys), dev(vals)
+    if in_place:
+        ok, ov = I.sort_pairs(kd, vd, out_keys=kd, out_vals=vd, algo="bucket", num_buckets=B)
+    else:
+        ok, ov = I.sort_pairs(kd, vd, algo="bucket", num_buckets=B)
+    ref = oracle.radix_lsd(keys, vals)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+    out = I.sort(dev(keys), algo="bucket", num_buckets=B)
+    np.testing.assert_array_equal(host(out), ref.keys)
+    assert I.device_error(0) == 0
