@@ -47,7 +47,8 @@ template <typename K>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restrict__ keys, uint64_t n,
                                                                const uint64_t *__restrict__ minmax, uint32_t B,
                                                                uint32_t passes, uint32_t *__restrict__ subhist,
-                                                               const uint64_t *skip, uint64_t *order)
+                                                               const uint64_t *skip, uint64_t *order,
+                                                               uint64_t *above)
 {
     // SUBHIST_COPIES copies of the counts, lane l adding into copy
     // l % SUBHIST_COPIES: lanes of one instruction meet on a bank or a word
@@ -56,14 +57,17 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
     __shared__ uint32_t s_h[SUBHIST_WORDS * SUBHIST_COPIES];
     if (skip && *skip) return;   // keys already sorted
     // with `order`, also whether the keys are already sorted
+    // (and with `above`, whether a key exceeds the range's maximum)
     const bool check = order != nullptr;
-    bool order_ok = true;
+    bool order_ok = true, high = false;
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
+    const K kmax = (K)minmax[1];
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS * SUBHIST_COPIES; i += BK_THREADS) s_h[i] = 0;
     __syncthreads();
     uint32_t *my_h = s_h + threadIdx.x % SUBHIST_COPIES;
     auto count = [&](K k) {
         const uint32_t b = bucket_of(m, k);
+        high |= k > kmax;
         for (uint32_t p = 0; p < passes; p++) atomicAdd(my_h + (p * 256 + ((b >> (8 * p)) & 255u)) * SUBHIST_COPIES, 1u);
     };
     constexpr int KPV = 16 / (int)sizeof(K);
@@ -86,6 +90,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
     } else {
         __syncthreads();
     }
+    if (above && __syncthreads_or(high) && threadIdx.x == 0) *above = 1;
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS) {
         uint32_t c = 0;
 #pragma unroll
@@ -110,13 +115,16 @@ struct BucketPlanArgs {
                               // input (keys or values): start in the scratch buffer
     const uint64_t *minmax;
     uint64_t *bucket_skip;    // set here: what the per-bucket sorts do (BSKIP_*)
+    const uint64_t *above;    // declared range: nonzero when some key lies above it
 };
 
 // the per-bucket stage after the scatter: BSKIP_NONE sorts every bucket;
 // BSKIP_SORTED does nothing (the input was already in order and is copied);
 // BSKIP_SINGLE does nothing either, because B >= R: then b(k) is strictly
-// increasing in k, every bucket holds copies of one key value, and the
-// scattered keys are already the sorted output (they are copied there)
+// increasing on [min, max], every bucket holds copies of one key value, and
+// the scattered keys are already the sorted output (they are copied there).
+// Keys above a declared bound all go to the last bucket, which can then hold
+// several values: with any such key the buckets are sorted as usual.
 constexpr uint64_t BSKIP_NONE = 0, BSKIP_SORTED = 1, BSKIP_SINGLE = 2;
 
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
@@ -127,7 +135,8 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_plan(BucketPlanArgs a)
     uint32_t *f = a.plan + MAX_PASSES * PLAN_WORDS;   // final-copy words
     if (tid == 0) {
         const uint64_t range_m1 = a.minmax[1] - a.minmax[0];   // R - 1
-        *a.bucket_skip = *a.skip ? BSKIP_SORTED : (range_m1 < (uint64_t)a.B ? BSKIP_SINGLE : BSKIP_NONE);
+        const bool single = range_m1 < (uint64_t)a.B && !(a.above && *a.above);
+        *a.bucket_skip = *a.skip ? BSKIP_SORTED : (single ? BSKIP_SINGLE : BSKIP_NONE);
     }
     if (*a.skip) {
         if (tid == 0) {
@@ -330,11 +339,12 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_start_runs(const StartRun
 
 // the declared range [0, key_bound] in place of a measured one; whether
 // the keys are in order is then found by the bucket histogram
-__global__ void k_set_range(uint64_t *minmax, uint64_t lo, uint64_t hi, uint64_t *sorted)
+__global__ void k_set_range(uint64_t *minmax, uint64_t lo, uint64_t hi, uint64_t *sorted, uint64_t *above)
 {
     minmax[0] = lo;
     minmax[1] = hi;
     *sorted = 1;
+    *above = 0;
 }
 
 // With one key value per bucket the scattered keys (and values) are the
@@ -445,7 +455,8 @@ BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_
     auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes, 256); return at; };
     L.counters = take((size_t)CTR_WORDS * 4);
     L.plan = take((size_t)(MAX_PASSES + 1) * PLAN_WORDS * 4);
-    L.minmax = take(32);   // min, max, whether the keys are already sorted, the per-bucket stage
+    L.minmax = take(40);   // min, max, whether the keys are already sorted, the per-bucket stage,
+                           // whether a key lies above a declared range
     L.counts = take(L.buckets <= BUCKET_LDS_HIST_MAX ? (size_t)L.buckets * 4 : 0);
     L.subhist = take((size_t)SUBHIST_WORDS * 4);
     L.excl = take((size_t)L.scatter_passes * radix * 4);
@@ -476,6 +487,7 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     uint64_t *minmax = reinterpret_cast<uint64_t *>(ws + L.minmax);
     uint64_t *sorted = minmax + 2;
     uint64_t *bskip = minmax + 3;
+    uint64_t *above = minmax + 4;
     uint32_t *counts = reinterpret_cast<uint32_t *>(ws + L.counts);
     uint32_t *subhist = reinterpret_cast<uint32_t *>(ws + L.subhist);
     uint32_t *excl = reinterpret_cast<uint32_t *>(ws + L.excl);
@@ -500,11 +512,12 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     // the bucket histogram): then every later stage finds nothing to do and
     // the output is a copy of the input
     const bool bound = c.opts.key_bound != 0;
-    if (bound) hipLaunchKernelGGL(k_set_range, dim3(1), dim3(1), 0, s, minmax, 0ull, c.opts.key_bound, sorted);
+    if (bound) hipLaunchKernelGGL(k_set_range, dim3(1), dim3(1), 0, s, minmax, 0ull, c.opts.key_bound, sorted, above);
     else e = minmax_run((int)sizeof(K), c.keys_in, c.n, minmax, s, sorted);
     if (e != hipSuccess) return e;
     const uint64_t *hist_skip = bound ? nullptr : sorted;
     uint64_t *hist_order = bound ? sorted : nullptr;
+    uint64_t *hist_above = bound ? above : nullptr;   // measured: no key lies above the maximum
     auto copy_if_sorted = [&]() {
         if (c.keys_in == c.keys_out && (!PAIRS || c.vals_in == c.vals_out)) return;
         const uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
@@ -515,13 +528,14 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     if (tm) tm->mark(INTSORT_KERNEL_MINMAX, 0, s);
     const bool full_hist = B <= BUCKET_LDS_HIST_MAX;
     if (full_hist) {
-        e = bucket_histogram_run((int)sizeof(K), c.keys_in, c.n, minmax, B, counts, s, hist_skip, hist_order);
+        e = bucket_histogram_run_above((int)sizeof(K), c.keys_in, c.n, minmax, B, counts, s, hist_skip, hist_order,
+                                       hist_above);
     } else {
         hipLaunchKernelGGL(k_fill<uint32_t>, dim3(4), dim3(256), 0, s, subhist, (uint64_t)SUBHIST_WORDS, 0u);
         uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
         hipLaunchKernelGGL((k_bucket_subhist<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
                            s, static_cast<const K *>(c.keys_in), c.n, minmax, B, L.scatter_passes, subhist, hist_skip,
-                           hist_order);
+                           hist_order, hist_above);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -530,7 +544,8 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     // scatters into its own buffers)
     const bool alias = c.keys_in == c.keys_out || (PAIRS && c.vals_in == c.vals_out);
     BucketPlanArgs pa{counts, subhist, excl, offsets, plan, B, (uint32_t)C::RADIX, L.scatter_passes,
-                      full_hist ? 1u : 0u, c.n, sorted, scatter_only && alias ? 1u : 0u, minmax, bskip};
+                      full_hist ? 1u : 0u, c.n, sorted, scatter_only && alias ? 1u : 0u, minmax, bskip,
+                      bound ? above : nullptr};
     hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(BK_THREADS), 0, s, pa);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(fill_grid), dim3(256), 0, s, status0,
                        (uint64_t)L.num_tiles * C::RADIX, 0u);

@@ -8,6 +8,7 @@
 #include "bucket_map.hpp"
 #include "device_common.hpp"
 #include "internal.hpp"
+#include "sort_plans.hpp"
 
 namespace intsort {
 
@@ -121,21 +122,26 @@ template <typename K, bool LDS>
 __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__restrict__ keys, uint64_t n,
                                                                  const uint64_t *__restrict__ minmax,
                                                                  uint32_t B, uint32_t *__restrict__ counts,
-                                                                 const uint64_t *skip, uint64_t *order)
+                                                                 const uint64_t *skip, uint64_t *order,
+                                                                 uint64_t *above)
 {
     __shared__ uint32_t s_c[LDS ? BH_LDS_BUCKETS : 1];
     if (skip && *skip) return;   // keys already sorted: nothing to count
     // with `order`, also whether the keys are already sorted (cleared by a
-    // workgroup that finds a key smaller than the one before it)
+    // workgroup that finds a key smaller than the one before it); with
+    // `above`, whether a key exceeds the range's maximum (set to 1 by a
+    // workgroup that finds one: a declared bound the keys do not keep)
     const bool check = order != nullptr;
-    bool order_ok = true;
+    bool order_ok = true, high = false;
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
+    const K kmax = (K)minmax[1];
     if (LDS) {
         for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) s_c[i] = 0;
         __syncthreads();
     }
     auto count = [&](K k) {
         const uint32_t b = bucket_of(m, k);
+        high |= k > kmax;
         if (LDS) lds_count(s_c, b);
         else atomicAdd(&counts[b], 1u);
     };
@@ -166,6 +172,7 @@ __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__rest
         if (check && i > 0 && keys[i] < keys[i - 1]) order_ok = false;
     }
     if (check && __syncthreads_or(!order_ok) && threadIdx.x == 0) *order = 0;
+    if (above && __syncthreads_or(high) && threadIdx.x == 0) *above = 1;
     if (LDS) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) {
@@ -179,6 +186,13 @@ hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, con
                                 uint32_t B, uint32_t *counts, hipStream_t s, const uint64_t *skip,
                                 uint64_t *order)
 {
+    return bucket_histogram_run_above(key_bytes, keys, n, minmax, B, counts, s, skip, order, nullptr);
+}
+
+hipError_t bucket_histogram_run_above(int key_bytes, const void *keys, uint64_t n, const uint64_t *minmax,
+                                      uint32_t B, uint32_t *counts, hipStream_t s, const uint64_t *skip,
+                                      uint64_t *order, uint64_t *above)
+{
     int dev = 0;
     (void)hipGetDevice(&dev);
     hipLaunchKernelGGL(k_zero_u32, dim3((B + 255) / 256), dim3(256), 0, s, counts, B);
@@ -189,12 +203,12 @@ hipError_t bucket_histogram_run(int key_bytes, const void *keys, uint64_t n, con
     const bool lds = B <= BH_LDS_BUCKETS;
     if (key_bytes == 4) {
         auto kp = static_cast<const uint32_t *>(keys);
-        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint32_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order);
-        else hipLaunchKernelGGL((k_bucket_histogram<uint32_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order);
+        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint32_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order, above);
+        else hipLaunchKernelGGL((k_bucket_histogram<uint32_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order, above);
     } else {
         auto kp = static_cast<const uint64_t *>(keys);
-        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint64_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order);
-        else hipLaunchKernelGGL((k_bucket_histogram<uint64_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order);
+        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint64_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order, above);
+        else hipLaunchKernelGGL((k_bucket_histogram<uint64_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order, above);
     }
     return hipGetLastError();
 }

@@ -43,6 +43,11 @@ struct BucketCall {
 
 BucketLayout bucket_layout(int key_bytes, bool pairs, uint64_t n, const intsort_options &o);
 hipError_t bucket_sort_run(const BucketCall &c, hipStream_t s);
+// bucket_histogram_run that also sets *above to 1 when some key exceeds
+// minmax[1] (above may be null)
+hipError_t bucket_histogram_run_above(int key_bytes, const void *keys, uint64_t n, const uint64_t *minmax,
+                                      uint32_t B, uint32_t *counts, hipStream_t s, const uint64_t *skip,
+                                      uint64_t *order, uint64_t *above);
 
 
 struct SegCall {

@@ -284,3 +284,30 @@ def test_one_value_per_bucket(dtype, span, B, in_place):
     out = I.sort(dev(keys), algo="bucket", num_buckets=B)
     np.testing.assert_array_equal(host(out), ref.keys)
     assert I.device_error(0) == 0
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("bound,B", [(999, 1000), (999, 4096), (59_999, 65536), (59_999, 60_000)])
+def test_keys_above_declared_bound(dtype, bound, B):
+    """A declared bound the keys do not keep: keys above it go to the last
+    bucket, which then holds several values although B >= bound + 1, so the
+    buckets must still be sorted.  Keys within the bound alone take the
+    one-value-per-bucket shortcut."""
+    n = 200_003
+    rng = np.random.default_rng(bound + B)
+    keys = rng.integers(0, bound + 1, n).astype(dtype)
+    vals = np.arange(n, dtype=np.uint32)
+    ref = oracle.radix_lsd(keys, vals)
+    ok, ov = I.sort_pairs(dev(keys), dev(vals), algo="bucket", num_buckets=B, key_bound=bound)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+    hi = keys.copy()
+    pos = rng.choice(n, 50, replace=False)
+    hi[pos] = (rng.integers(bound + 1, 4 * bound, 50)).astype(dtype)
+    ref = oracle.radix_lsd(hi, vals)
+    ok, ov = I.sort_pairs(dev(hi), dev(vals), algo="bucket", num_buckets=B, key_bound=bound)
+    np.testing.assert_array_equal(host(ok), ref.keys)
+    np.testing.assert_array_equal(host(ov), ref.vals)
+    out = I.sort(dev(hi), algo="bucket", num_buckets=B, key_bound=bound)
+    np.testing.assert_array_equal(host(out), ref.keys)
+    assert I.device_error(0) == 0
