@@ -34,7 +34,10 @@ def test_bucket_histogram_parity(dtype, B, hi):
 @pytest.mark.parametrize("dtype,mn,mx,B", [(np.uint32, 0, 2**32 - 1, 1024), (np.uint32, 17, 1040, 7),
                                            (np.uint64, 0, 2**64 - 1, 65536), (np.uint64, 2**40 + 3, 2**41, 1000),
                                            (np.uint32, 5, 5, 3), (np.uint32, 0, 999, 1024),
-                                           # 64-bit ranges above 2^62: the 128-bit correction loop
+                                           # 32-bit keys with B >= R (a = floor(B / R) of 3 and 1) and B = 2^24
+                                           (np.uint32, 100, 399, 1000), (np.uint32, 7, 7 + 2**20 - 1, 2**20),
+                                           (np.uint32, 0, 2**32 - 1, 2**24),
+                                           # 64-bit ranges above 2^62: the remainder needs more than 64 bits
                                            (np.uint64, 3, 2**63 + 2**61 + 2, 1000),
                                            (np.uint64, 3, 2**63 + 2**61 + 2, 65536),
                                            (np.uint64, 2**64 - 2**62 - 7, 2**64 - 1, 777),
@@ -44,9 +47,10 @@ def test_bucket_histogram_parity(dtype, B, hi):
 def test_bucket_map_at_boundaries(dtype, mn, mx, B):
     """Keys on both sides of every bucket boundary (sampled for large B),
     plus min and max: the device histogram of these keys equals the oracle's.
-    For 64-bit keys the device takes b(k) from a double estimate with one
-    correction while R <= 2^62 and from a 128-bit correction loop above, so
-    ranges on either side of 2^62 and up to 2^64 are covered."""
+    For 64-bit keys the device takes b(k) from a double estimate and one
+    exact 96-bit remainder check, whose operands grow with R: ranges on
+    either side of 2^62 and up to 2^64 are covered; 32-bit keys take one
+    fixed-point product, also with B >= R (a = floor(B / R) > 0)."""
     R = mx - mn + 1
     js = range(1, B) if B <= 1024 else list(range(1, 300)) + list(range(B - 300, B))
     ks = [mn, mx]
