@@ -43,7 +43,7 @@ constexpr uint32_t SUBHIST_COPIES = 8;     // 32 KB of LDS counts per workgroup
 constexpr uint64_t WINDOW_AVG = 64;       // below this many keys per bucket, windows
 
 // counts of every byte of b(k) that a scatter pass sorts on
-template <typename K>
+template <typename K, bool ABOVE>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restrict__ keys, uint64_t n,
                                                                const uint64_t *__restrict__ minmax, uint32_t B,
                                                                uint32_t passes, uint32_t *__restrict__ subhist,
@@ -57,17 +57,17 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
     __shared__ uint32_t s_h[SUBHIST_WORDS * SUBHIST_COPIES];
     if (skip && *skip) return;   // keys already sorted
     // with `order`, also whether the keys are already sorted
-    // (and with `above`, whether a key exceeds the range's maximum)
+    // (and with ABOVE, whether a key exceeds the range's maximum)
     const bool check = order != nullptr;
-    bool order_ok = true, high = false;
+    bool order_ok = true;
+    K seen = 0;   // largest key this thread counted (ABOVE)
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
-    const K kmax = (K)minmax[1];
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS * SUBHIST_COPIES; i += BK_THREADS) s_h[i] = 0;
     __syncthreads();
     uint32_t *my_h = s_h + threadIdx.x % SUBHIST_COPIES;
     auto count = [&](K k) {
         const uint32_t b = bucket_of(m, k);
-        high |= k > kmax;
+        if (ABOVE) seen = seen > k ? seen : k;
         for (uint32_t p = 0; p < passes; p++) atomicAdd(my_h + (p * 256 + ((b >> (8 * p)) & 255u)) * SUBHIST_COPIES, 1u);
     };
     constexpr int KPV = 16 / (int)sizeof(K);
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_subhist(const K *__restri
     } else {
         __syncthreads();
     }
-    if (above && __syncthreads_or(high) && threadIdx.x == 0) *above = 1;
+    if (ABOVE && __syncthreads_or(seen > (K)minmax[1]) && threadIdx.x == 0) *above = 1;
     for (uint32_t i = threadIdx.x; i < SUBHIST_WORDS; i += BK_THREADS) {
         uint32_t c = 0;
 #pragma unroll
@@ -533,9 +533,13 @@ static hipError_t bucket_run_typed(const BucketCall &c, hipStream_t s)
     } else {
         hipLaunchKernelGGL(k_fill<uint32_t>, dim3(4), dim3(256), 0, s, subhist, (uint64_t)SUBHIST_WORDS, 0u);
         uint64_t blocks = std::min<uint64_t>((c.n + BK_THREADS - 1) / BK_THREADS, (uint64_t)fill_grid * 2);
-        hipLaunchKernelGGL((k_bucket_subhist<K>), dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(BK_THREADS), 0,
-                           s, static_cast<const K *>(c.keys_in), c.n, minmax, B, L.scatter_passes, subhist, hist_skip,
-                           hist_order, hist_above);
+        const dim3 g((uint32_t)std::max<uint64_t>(blocks, 1)), t(BK_THREADS);
+        if (hist_above)
+            hipLaunchKernelGGL((k_bucket_subhist<K, true>), g, t, 0, s, static_cast<const K *>(c.keys_in), c.n, minmax,
+                               B, L.scatter_passes, subhist, hist_skip, hist_order, hist_above);
+        else
+            hipLaunchKernelGGL((k_bucket_subhist<K, false>), g, t, 0, s, static_cast<const K *>(c.keys_in), c.n, minmax,
+                               B, L.scatter_passes, subhist, hist_skip, hist_order, hist_above);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;

@@ -118,7 +118,7 @@ __global__ void k_zero_u32(uint32_t *p, uint32_t n)
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-template <typename K, bool LDS>
+template <typename K, bool LDS, bool ABOVE>
 __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__restrict__ keys, uint64_t n,
                                                                  const uint64_t *__restrict__ minmax,
                                                                  uint32_t B, uint32_t *__restrict__ counts,
@@ -129,19 +129,19 @@ __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__rest
     if (skip && *skip) return;   // keys already sorted: nothing to count
     // with `order`, also whether the keys are already sorted (cleared by a
     // workgroup that finds a key smaller than the one before it); with
-    // `above`, whether a key exceeds the range's maximum (set to 1 by a
+    // ABOVE, whether a key exceeds the range's maximum (*above set to 1 by a
     // workgroup that finds one: a declared bound the keys do not keep)
     const bool check = order != nullptr;
-    bool order_ok = true, high = false;
+    bool order_ok = true;
+    K seen = 0;   // largest key this thread counted (ABOVE)
     const BucketMap m = make_bucket_map(minmax[0], minmax[1], B);
-    const K kmax = (K)minmax[1];
     if (LDS) {
         for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) s_c[i] = 0;
         __syncthreads();
     }
     auto count = [&](K k) {
         const uint32_t b = bucket_of(m, k);
-        high |= k > kmax;
+        if (ABOVE) seen = seen > k ? seen : k;
         if (LDS) lds_count(s_c, b);
         else atomicAdd(&counts[b], 1u);
     };
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(BH_THREADS) void k_bucket_histogram(const K *__rest
         if (check && i > 0 && keys[i] < keys[i - 1]) order_ok = false;
     }
     if (check && __syncthreads_or(!order_ok) && threadIdx.x == 0) *order = 0;
-    if (above && __syncthreads_or(high) && threadIdx.x == 0) *above = 1;
+    if (ABOVE && __syncthreads_or(seen > (K)minmax[1]) && threadIdx.x == 0) *above = 1;
     if (LDS) {
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < B; i += BH_THREADS) {
@@ -201,15 +201,17 @@ hipError_t bucket_histogram_run_above(int key_bytes, const void *keys, uint64_t 
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
     const bool lds = B <= BH_LDS_BUCKETS;
-    if (key_bytes == 4) {
-        auto kp = static_cast<const uint32_t *>(keys);
-        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint32_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order, above);
-        else hipLaunchKernelGGL((k_bucket_histogram<uint32_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order, above);
-    } else {
-        auto kp = static_cast<const uint64_t *>(keys);
-        if (lds) hipLaunchKernelGGL((k_bucket_histogram<uint64_t, true>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order, above);
-        else hipLaunchKernelGGL((k_bucket_histogram<uint64_t, false>), dim3((uint32_t)blocks), dim3(BH_THREADS), 0, s, kp, n, minmax, B, counts, skip, order, above);
-    }
+    auto go = [&](auto key_tag) {
+        using K = decltype(key_tag);
+        auto kp = static_cast<const K *>(keys);
+        const dim3 g((uint32_t)blocks), t(BH_THREADS);
+        if (lds && above) hipLaunchKernelGGL((k_bucket_histogram<K, true, true>), g, t, 0, s, kp, n, minmax, B, counts, skip, order, above);
+        else if (lds) hipLaunchKernelGGL((k_bucket_histogram<K, true, false>), g, t, 0, s, kp, n, minmax, B, counts, skip, order, above);
+        else if (above) hipLaunchKernelGGL((k_bucket_histogram<K, false, true>), g, t, 0, s, kp, n, minmax, B, counts, skip, order, above);
+        else hipLaunchKernelGGL((k_bucket_histogram<K, false, false>), g, t, 0, s, kp, n, minmax, B, counts, skip, order, above);
+    };
+    if (key_bytes == 4) go(uint32_t{});
+    else go(uint64_t{});
     return hipGetLastError();
 }
 

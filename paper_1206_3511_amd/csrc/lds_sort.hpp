@@ -235,4 +235,153 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
     }
 }
 
+// The same sort for segments of 64-bit keys, which differ in up to eight
+// bytes.  Every key's varying bytes go once into byte planes in LDS, and the
+// passes move 16-bit element indices instead of the keys and values: a pass
+// reads one digit byte and writes and reads one index per key, against eight
+// key and four value bytes written and read.  The sorted keys and values are
+// gathered from the segment's input at the end (every gather is done before
+// any store, so the sort may run in place).
+template <typename K, bool PAIRS, int NT, int IPT, class Src>
+__global__ __launch_bounds__(NT) void k_lds_sort_idx(LdsSortArgs<Src> a)
+{
+    constexpr int WAVES = NT / WAVE;
+    constexpr int TILE = NT * IPT;
+    constexpr int RADIX = 256;
+    constexpr int KB = (int)sizeof(K);
+    constexpr int DPT = RADIX > NT ? RADIX / NT : 1;
+    static_assert(TILE <= 65536, "16-bit element indices");
+    __shared__ uint8_t s_dig[KB * TILE];    // byte p of element e at s_dig[p * TILE + e]
+    __shared__ uint16_t s_idx[TILE];
+    __shared__ uint32_t s_wcnt[WAVES * RADIX];
+    __shared__ uint32_t s_excl[RADIX];
+    __shared__ uint32_t s_scan[WAVES + 1];
+    __shared__ K s_diff[WAVES];
+
+    uint32_t seg;
+    if (a.list) {
+        if (blockIdx.x >= *a.list_count) return;
+        seg = a.list[blockIdx.x];
+    } else {
+        if (blockIdx.x >= a.direct_count) return;
+        seg = blockIdx.x;
+    }
+    const K *kin;
+    K *kout;
+    const uint32_t *vin;
+    uint32_t *vout;
+    uint32_t m, base_unused;
+    a.src.template seg<K>(seg, kin, kout, vin, vout, m, base_unused);   // m <= TILE by classification
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    const uint32_t lofs = wave * (IPT * WAVE) + lane;
+    // slots of padding alone (index >= m for the whole wave) are skipped,
+    // as in k_lds_sort
+    const uint32_t wbase = __builtin_amdgcn_readfirstlane(wave * (uint32_t)(IPT * WAVE));
+    auto live = [&](int j) { return wbase + (uint32_t)(j * WAVE) < m; };
+
+    K k[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; j++) k[j] = lofs + j * WAVE < m ? kin[lofs + j * WAVE] : ~K(0);
+    const K ref = m > 0 ? kin[0] : K(0);
+    K diff = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; j++)
+        if (lofs + j * WAVE < m) diff |= k[j] ^ ref;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) diff |= __shfl_xor(diff, off, WAVE);
+    if (lane == 0) s_diff[wave] = diff;
+    __syncthreads();
+    diff = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; w++) diff |= s_diff[w];
+
+    // byte planes of the bytes that vary (padding keys are all ones, so
+    // their digits are the largest and they rank last)
+#pragma unroll
+    for (int p = 0; p < KB; p++) {
+        if (((diff >> (8 * p)) & 0xffu) == 0) continue;
+#pragma unroll
+        for (int j = 0; j < IPT; j++)
+            if (live(j)) s_dig[p * TILE + lofs + j * WAVE] = (uint8_t)(k[j] >> (8 * p));
+    }
+    uint32_t e[IPT];   // the element at each of this thread's positions
+#pragma unroll
+    for (int j = 0; j < IPT; j++) e[j] = lofs + j * WAVE;
+    __syncthreads();
+
+    uint32_t *wcnt = s_wcnt + wave * RADIX;
+    for (int p = 0; p < KB; p++) {
+        if (((diff >> (8 * p)) & 0xffu) == 0) continue;   // the same for every workgroup thread
+        for (uint32_t i = tid; i < (uint32_t)(WAVES * RADIX); i += NT) s_wcnt[i] = 0;
+        __syncthreads();
+        const uint8_t *plane = s_dig + p * TILE;
+        uint32_t d[IPT], rk[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; j++) {
+            d[j] = 0;
+            rk[j] = 0;
+            if (!live(j)) continue;
+            d[j] = plane[e[j]];
+            rk[j] = wave_rank_atomic(d[j], wcnt);
+        }
+        __syncthreads();
+        uint32_t tcnt[DPT];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < DPT; i++) {
+            const uint32_t dd = tid * DPT + i;
+            tcnt[i] = 0;
+            if (dd < (uint32_t)RADIX) {
+                uint32_t run = 0;
+#pragma unroll
+                for (int w = 0; w < WAVES; w++) {
+                    const uint32_t c = s_wcnt[w * RADIX + dd];
+                    s_wcnt[w * RADIX + dd] = run;
+                    run += c;
+                }
+                tcnt[i] = run;
+            }
+            mine += tcnt[i];
+        }
+        uint32_t total_unused;
+        uint32_t ex = block_exclusive_scan<NT>(mine, s_scan, &total_unused);
+#pragma unroll
+        for (int i = 0; i < DPT; i++) {
+            const uint32_t dd = tid * DPT + i;
+            if (dd < (uint32_t)RADIX) s_excl[dd] = ex;
+            ex += tcnt[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; j++) {
+            if (!live(j)) continue;
+            s_idx[s_excl[d[j]] + s_wcnt[wave * RADIX + d[j]] + rk[j]] = (uint16_t)e[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; j++)
+            if (live(j)) e[j] = s_idx[lofs + j * WAVE];
+        __syncthreads();
+    }
+    // the first m positions hold the real elements in sorted order; every
+    // gather completes before the barrier, so no store overwrites a key or
+    // value another thread still reads
+    uint32_t v[PAIRS ? IPT : 1];
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        if (lofs + j * WAVE < m) {
+            k[j] = kin[e[j]];
+            if (PAIRS) v[j] = vin[e[j]];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        if (lofs + j * WAVE < m) {
+            kout[lofs + j * WAVE] = k[j];
+            if (PAIRS) vout[lofs + j * WAVE] = v[j];
+        }
+    }
+}
+
 }  // namespace intsort

@@ -361,7 +361,9 @@ template <typename K, bool PAIRS, int NT, int IPT, class Src>
 static void launch_lds_class(const LdsSortArgs<Src> &la, uint32_t grid, hipStream_t s)
 {
     if (grid == 0) return;
-    hipLaunchKernelGGL((k_lds_sort<K, PAIRS, NT, IPT, Src>), dim3(grid), dim3(NT), 0, s, la);
+    // 64-bit keys differ in up to eight bytes: their passes move indices
+    if constexpr (sizeof(K) == 8) hipLaunchKernelGGL((k_lds_sort_idx<K, PAIRS, NT, IPT, Src>), dim3(grid), dim3(NT), 0, s, la);
+    else hipLaunchKernelGGL((k_lds_sort<K, PAIRS, NT, IPT, Src>), dim3(grid), dim3(NT), 0, s, la);
 }
 
 static void set_bufs(SegTiles &, const SegBuf *) {}
