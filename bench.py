@@ -433,10 +433,12 @@ def run_batched(name, p, args):
     ctx = I.context(0)
     from paper_1206_3511_amd import autotune
 
-    choice = autotune.tuned_options("segmented", 4, N)
-    tuned_now = not choice
+    cut = autotune.tuned_options("segmented", 4, N)
+    bits = autotune.tuned_options("segmented_bits", 4, N)
+    choice = {**cut, **bits}
+    tuned_now = not (cut and bits)
     if tuned_now:
-        print(f"bench[{name}]: autotuning the LDS cutoff", file=sys.stderr, flush=True)
+        print(f"bench[{name}]: autotuning the LDS cutoff and digit width", file=sys.stderr, flush=True)
         choice = autotune.tune_segmented(k, offs)
     fn = lambda: I.segmented_sort(k, offs, out_keys=out, **choice)  # noqa: E731
     steps = max(1, args.steps // 4)

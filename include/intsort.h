@@ -135,9 +135,13 @@ typedef INTSORT_ENUM(intsort_algo) {
  * take it; otherwise the library default given below.  Other zero fields
  * mean the library default.  A NULL options pointer means all zero.
  *   digit_bits   radix digit width r: 0 (tuned for plain radix sorts of
- *                unsigned keys, else 8) | 4 | 8 | 11.  The
- *                number of passes is ceil(key_bits / r) (Algorithm 4's d
- *                for a key of key_bits bits).
+ *                unsigned keys and for segmented and batched calls, else
+ *                8) | 4 | 8 | 11.  The number of passes is
+ *                ceil(key_bits / r) (Algorithm 4's d for a key of key_bits
+ *                bits).  Segmented and batched calls take 4 or 8 (the
+ *                digit passes of segments longer than lds_cutoff; shorter
+ *                ones are sorted on chip, with the same result) and return
+ *                INTSORT_ERR_UNSUPPORTED for 11.
  *   num_buckets  bucket sort: number of buckets B, 1..2^30 (default 1024
  *                for u32, 65536 for u64).  The bucket of key k is
  *                floor((k - min) * B / (max - min + 1)), exact.
@@ -183,8 +187,9 @@ const char *intsort_status_string(intsort_status s);
  * fields take; any choice gives the same bytes, only the speed differs).
  * A text file, one entry per line, tab-separated:
  *   device key, kind, key bytes (4 | 8), size class, value
- * with kind "radix" (value: digit_bits), "bucket" (num_buckets) or
- * "segmented" (lds_cutoff).  The device key is the one intsort_device_key
+ * with kind "radix" (value: digit_bits), "bucket" (num_buckets),
+ * "segmented" (lds_cutoff) or "segmented_bits" (digit_bits of segmented and
+ * batched calls).  The device key is the one intsort_device_key
  * gives; "*" matches every device (and a planning context, whose key is
  * empty).  '#' starts a comment line; lines that do not parse, and values a
  * call cannot take, are ignored.  intsort_create loads the file named by

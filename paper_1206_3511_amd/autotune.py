@@ -11,6 +11,8 @@ choice:
   bucket     number of buckets B               (num_buckets)
   segmented  LDS cutoff: segments up to it are sorted by one workgroup in
              LDS, longer ones by all workgroups (lds_cutoff)
+  segmented_bits  digit width r in {4, 8} of those longer segments' passes
+             (digit_bits of segmented and batched calls)
 
 The table lives in $INTSORT_TUNE_FILE, else ~/.cache/intsort/tune.tsv.  The
 device key comes from the library (intsort_device_key), so both sides agree
@@ -28,9 +30,11 @@ import torch
 from . import intsort as I
 
 RADIX_BITS = (4, 8, 11)
+SEG_BITS = (4, 8)
 BUCKETS = (256, 1024, 4096, 16384, 65536)
 CUTOFFS = (256, 2048, 8192, 16384)
-FIELDS = {"radix": "digit_bits", "bucket": "num_buckets", "segmented": "lds_cutoff"}
+FIELDS = {"radix": "digit_bits", "bucket": "num_buckets", "segmented": "lds_cutoff",
+          "segmented_bits": "digit_bits"}
 
 
 def table_path() -> str:
@@ -117,15 +121,21 @@ def tune_bucket(width: int, n: int, device: int = 0) -> dict:
 
 
 def tune_segmented(keys: torch.Tensor, offsets: torch.Tensor, device: int = 0) -> dict:
-    """Tunes the LDS cutoff on a real batch (keys packed, device offsets)."""
+    """Tunes the LDS cutoff, then the digit width of the longer segments'
+    passes with that cutoff, on a real batch (keys packed, device offsets)."""
     out = torch.empty_like(keys)
     width = keys.element_size()
     ms = {}
     for c in CUTOFFS:
         if width == 8 and c > 8192:
             continue
-        ms[c] = _time(lambda: I.segmented_sort(keys, offsets, out_keys=out, lds_cutoff=c), reps=3)
-    return _record("segmented", width, keys.numel(), min(ms, key=ms.get), device)
+        ms[c] = _time(lambda: I.segmented_sort(keys, offsets, out_keys=out, lds_cutoff=c, digit_bits=8), reps=3)
+    cut = min(ms, key=ms.get)
+    msr = {r: _time(lambda: I.segmented_sort(keys, offsets, out_keys=out, lds_cutoff=cut, digit_bits=r), reps=3)
+           for r in SEG_BITS}
+    _record("segmented", width, keys.numel(), cut, device, reload=False)
+    return {**_record("segmented_bits", width, keys.numel(), min(msr, key=msr.get), device),
+            "lds_cutoff": cut}
 
 
 def tuned_options(kind: str, width: int, n: int, device: int = 0) -> dict:

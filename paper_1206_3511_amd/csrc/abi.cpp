@@ -84,6 +84,9 @@ intsort_status read_opts(const intsort_ctx *ctx, const intsort_options *in, ints
             out->num_buckets = v;
         if (out->lds_cutoff == 0 && segmented && tune_lookup(ctx->tune, ctx->dev_key, TUNE_LDS_CUTOFF, w, n, &v))
             out->lds_cutoff = v;
+        if (out->digit_bits == 0 && segmented &&
+            tune_lookup(ctx->tune, ctx->dev_key, TUNE_SEG_BITS, w, n, &v) && (v == 4 || v == 8))
+            out->digit_bits = v;
     }
     if (out->digit_bits == 0) out->digit_bits = 8;
     if (out->digit_bits != 4 && out->digit_bits != 8 && out->digit_bits != 11) return INTSORT_ERR_UNSUPPORTED;
@@ -444,6 +447,7 @@ static intsort_status segmented_common(intsort_ctx *ctx, intsort_key_type kt, co
     if (st != INTSORT_OK) return st;
     if (num_segments == 0 && n_total != 0) return INTSORT_ERR_INVALID_ARGUMENT;
     if (n_total == 0 || num_segments == 0) return INTSORT_OK;
+    if (o.digit_bits != 4 && o.digit_bits != 8) return INTSORT_ERR_UNSUPPORTED;
     if (!d_offsets || !keys_in || !keys_out) return INTSORT_ERR_INVALID_ARGUMENT;
     if (pairs && (!vals_in || !vals_out)) return INTSORT_ERR_INVALID_ARGUMENT;
     if (!aligned16(keys_in) || !aligned16(keys_out)) return INTSORT_ERR_MISALIGNED;
@@ -513,7 +517,7 @@ intsort_status intsort_batched_sort_keys(intsort_ctx *ctx, intsort_key_type kt, 
         if (st != INTSORT_OK) return st;
         if (count == 0 || total_keys == 0) return INTSORT_OK;
         if (!d_descs) return INTSORT_ERR_INVALID_ARGUMENT;
-        if (o.digit_bits != 8) return INTSORT_ERR_UNSUPPORTED;
+        if (o.digit_bits != 4 && o.digit_bits != 8) return INTSORT_ERR_UNSUPPORTED;
         if (total_keys > MAX_KEYS || count > MAX_SEGMENTS) return INTSORT_ERR_UNSUPPORTED;
         const int kb = key_bytes_of(kt);
         const SegLayout L = segmented_layout(kb, false, total_keys, count, o);

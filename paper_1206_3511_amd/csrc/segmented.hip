@@ -40,8 +40,8 @@ struct SegWs {
     uint32_t *lists;          // [NCLASS][list_stride]
     uint32_t list_stride;
     TileDesc *tiles;          // [tile_cap]
-    uint32_t *tile_hist;      // [tile_cap][passes][256]
-    uint32_t *seg_excl;       // [passes][slot_cap][256]
+    uint32_t *tile_hist;      // [tile_cap][passes][radix]
+    uint32_t *seg_excl;       // [passes][slot_cap][radix]
     uint32_t *status0;
     uint32_t *status1;
     uint32_t tile_cap;
@@ -171,20 +171,21 @@ __global__ __launch_bounds__(256) void k_seg_classify(Src src, uint64_t num_segm
 // also clears the tile's look-back words for the first pass, and the first
 // tile of each segment clears the segment's digit totals, which
 // k_seg_slot_sum adds up next
-template <typename K>
+template <typename K, int BITS>
 __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__restrict__ keys, SegWs w)
 {
-    constexpr int PASSES = (int)sizeof(K);
-    __shared__ uint32_t s_h[PASSES * 256];
+    constexpr int PASSES = 8 * (int)sizeof(K) / BITS;
+    constexpr uint32_t RADIX = 1u << BITS;
+    __shared__ uint32_t s_h[PASSES * RADIX];
     const uint32_t t = blockIdx.x;
     if (t >= w.counters[CTR_SEG_TILES]) return;
     const TileDesc d = w.tiles[t];
     const K *kp = w.bufs ? static_cast<const K *>(w.bufs[d.slot].in) : keys;
     if (t == d.first_tile)
-        for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS)
-            w.seg_excl[((uint64_t)(i / 256) * w.slot_cap + d.slot) * 256 + i % 256] = 0;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS) s_h[i] = 0;
-    for (uint32_t i = threadIdx.x; i < 256u; i += SEG_HIST_THREADS) w.status0[(uint64_t)t * 256 + i] = 0;
+        for (uint32_t i = threadIdx.x; i < PASSES * RADIX; i += SEG_HIST_THREADS)
+            w.seg_excl[((uint64_t)(i / RADIX) * w.slot_cap + d.slot) * RADIX + i % RADIX] = 0;
+    for (uint32_t i = threadIdx.x; i < PASSES * RADIX; i += SEG_HIST_THREADS) s_h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < RADIX; i += SEG_HIST_THREADS) w.status0[(uint64_t)t * RADIX + i] = 0;
     __syncthreads();
     // U loads in flight per thread (segments start anywhere, so 4- or
     // 8-byte loads)
@@ -200,13 +201,14 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
         for (int u = 0; u < U; u++) {
             if (i0 + u * SEG_HIST_THREADS < d.count) {
 #pragma unroll
-                for (int p = 0; p < PASSES; p++) lds_count(s_h + p * 256, digit_at<K>(x[u], 8u * p, 0xffu));
+                for (int p = 0; p < PASSES; p++)
+                    lds_count(s_h + p * RADIX, digit_at<K>(x[u], (uint32_t)(BITS * p), RADIX - 1));
             }
         }
     }
     __syncthreads();
-    uint32_t *out = w.tile_hist + (uint64_t)t * PASSES * 256;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * 256); i += SEG_HIST_THREADS) out[i] = s_h[i];
+    uint32_t *out = w.tile_hist + (uint64_t)t * PASSES * RADIX;
+    for (uint32_t i = threadIdx.x; i < PASSES * RADIX; i += SEG_HIST_THREADS) out[i] = s_h[i];
 }
 
 // Digit totals of every large segment: each workgroup adds up the counts of
@@ -216,20 +218,23 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
 // workgroups instead of being walked by one.
 constexpr uint32_t SUM_TILES = 32;
 
-template <typename K>
+template <typename K, int BITS>
 __global__ __launch_bounds__(256) void k_seg_slot_sum(SegWs w)
 {
-    constexpr int PASSES = (int)sizeof(K);
+    constexpr int PASSES = 8 * (int)sizeof(K) / BITS;
+    constexpr uint32_t RADIX = 1u << BITS;
+    static_assert(RADIX <= 256, "one thread per digit");
     const uint32_t listed = min(w.counters[CTR_SEG_TILES], w.tile_cap);
     const uint32_t t0 = blockIdx.x * SUM_TILES;
     if (t0 >= listed) return;
     const uint32_t t1 = min(listed, t0 + SUM_TILES);
     const uint32_t d = threadIdx.x;
+    if (d >= RADIX) return;
     uint32_t acc[PASSES];
     auto flush = [&](uint32_t slot) {
 #pragma unroll
         for (int p = 0; p < PASSES; p++) {
-            if (acc[p]) atomicAdd(&w.seg_excl[((uint64_t)p * w.slot_cap + slot) * 256 + d], acc[p]);
+            if (acc[p]) atomicAdd(&w.seg_excl[((uint64_t)p * w.slot_cap + slot) * RADIX + d], acc[p]);
             acc[p] = 0;
         }
     };
@@ -243,32 +248,35 @@ __global__ __launch_bounds__(256) void k_seg_slot_sum(SegWs w)
             cur = slot;
         }
 #pragma unroll
-        for (int p = 0; p < PASSES; p++) acc[p] += w.tile_hist[((uint64_t)t * PASSES + p) * 256 + d];
+        for (int p = 0; p < PASSES; p++) acc[p] += w.tile_hist[((uint64_t)t * PASSES + p) * RADIX + d];
     }
     flush(cur);
 }
 
 // per large segment: exclusive scan of its digit totals per pass, and the
 // passes whose digit is not constant inside it
-template <typename K>
+template <typename K, int BITS>
 __global__ __launch_bounds__(256) void k_seg_scan(SegWs w)
 {
-    constexpr int PASSES = (int)sizeof(K);
+    constexpr int PASSES = 8 * (int)sizeof(K) / BITS;
+    constexpr uint32_t RADIX = 1u << BITS;
+    static_assert(PASSES <= 32, "one mask bit per pass");
     __shared__ uint32_t s_scan[256 / WAVE + 1];
     __shared__ uint32_t s_const;
     const uint32_t slot = blockIdx.x;
     if (slot >= w.counters[CTR_SEG_SLOTS] || slot >= w.slot_cap) return;
-    const uint32_t d = threadIdx.x;
+    const uint32_t d = threadIdx.x;   // a digit (threads past the radix count nothing)
     uint32_t mask = 0;
     for (int p = 0; p < PASSES; p++) {
-        const uint32_t c = w.seg_excl[((uint64_t)p * w.slot_cap + slot) * 256 + d];
+        uint32_t *e = w.seg_excl + ((uint64_t)p * w.slot_cap + slot) * RADIX;
+        const uint32_t c = d < RADIX ? e[d] : 0u;
         if (d == 0) s_const = 0;
         uint32_t total;
         const uint32_t ex = block_exclusive_scan<256>(c, s_scan, &total);
-        w.seg_excl[((uint64_t)p * w.slot_cap + slot) * 256 + d] = ex;
+        if (d < RADIX) e[d] = ex;
         // a digit that takes one value in the whole segment leaves the
         // segment's order as it is: the pass has nothing to do for it
-        if (c == total) s_const = 1;
+        if (d < RADIX && c == total) s_const = 1;
         __syncthreads();
         if (!(w.skip && s_const)) mask |= 1u << p;
         __syncthreads();
@@ -337,6 +345,8 @@ static SegLayout seg_layout_typed(uint64_t n, uint64_t S, uint32_t cutoff_req)
     L.lists = take((size_t)SegClasses<K>::NCLASS * S * 4);
     L.tiles = take((size_t)L.tile_cap * sizeof(TileDesc));
     L.bufs = take((size_t)L.slot_cap * sizeof(SegBuf));
+    // sized for 8-bit digits; the 4-bit counts (twice the passes, a
+    // sixteenth of the digits) fit in the same arrays
     L.tile_hist = take((size_t)L.tile_cap * PASSES * 256 * 4);
     L.seg_excl = take((size_t)PASSES * L.slot_cap * 256 * 4);
     L.slot_mask = take((size_t)L.slot_cap * 4);
@@ -371,12 +381,14 @@ static void set_bufs(DescTiles &t, const SegBuf *b) { t.bufs = b; }
 
 // the whole segmented sort for one key type; Src says where segments live,
 // Tiles how the digit passes of the large ones find their buffers
-template <typename K, bool PAIRS, class Src, class TilesT>
+template <typename K, bool PAIRS, class Src, class TilesT, int BITS>
 static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate, hipStream_t s)
 {
     using CL = SegClasses<K>;
-    using PC = PassCfg<K, 8>;
-    constexpr int PASSES = (int)sizeof(K);
+    using PC = PassCfg<K, BITS>;
+    static_assert(PassCfg<K, BITS>::TILE == PassCfg<K, 8>::TILE, "tiles listed at the 8-bit size");
+    constexpr int PASSES = 8 * (int)sizeof(K) / BITS;
+    constexpr uint32_t RADIX = 1u << BITS;
     const SegLayout &L = c.L;
     char *ws = c.ws;
     Timer *tm = c.timer;
@@ -444,11 +456,11 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     if (L.slot_cap == 0) return hipSuccess;   // no segment can be large
 
     // the large segments: digit counts per tile, offsets per segment, passes
-    hipLaunchKernelGGL((k_seg_tile_hist<K>), dim3(L.tile_cap), dim3(SEG_HIST_THREADS), 0, s,
+    hipLaunchKernelGGL((k_seg_tile_hist<K, BITS>), dim3(L.tile_cap), dim3(SEG_HIST_THREADS), 0, s,
                        static_cast<const K *>(c.keys_in), w);
     if (tm) tm->mark(INTSORT_KERNEL_DIGIT_HISTOGRAM, 0, s);
-    hipLaunchKernelGGL((k_seg_slot_sum<K>), dim3((L.tile_cap + SUM_TILES - 1) / SUM_TILES), dim3(256), 0, s, w);
-    hipLaunchKernelGGL((k_seg_scan<K>), dim3(L.slot_cap), dim3(256), 0, s, w);
+    hipLaunchKernelGGL((k_seg_slot_sum<K, BITS>), dim3((L.tile_cap + SUM_TILES - 1) / SUM_TILES), dim3(256), 0, s, w);
+    hipLaunchKernelGGL((k_seg_scan<K, BITS>), dim3(L.slot_cap), dim3(256), 0, s, w);
     if (tm) tm->mark(INTSORT_KERNEL_PLAN, 1, s);
 
     PassArgs<K> a{};
@@ -466,7 +478,7 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     TilesT tl{};
     tl.desc = w.tiles;
     tl.num_tiles = w.counters + CTR_SEG_TILES;
-    tl.radix = 256u;
+    tl.radix = RADIX;
     tl.slot_mask = w.slot_mask;
     // a pass must not read and write one buffer: keys or values in place
     // route every large segment's passes from the scratch buffer
@@ -475,9 +487,9 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     for (int p = 0; p < PASSES; p++) {
         a.plan = w.plan + p * PLAN_WORDS;
         a.pass = (uint32_t)p;
-        const RadixDigit dg{(uint32_t)(8 * p), 0xffu};
-        tl.seg_excl = w.seg_excl + (uint64_t)p * L.slot_cap * 256;
-        hipLaunchKernelGGL((k_onesweep<K, 8, PAIRS, RadixDigit, TilesT>), dim3(L.tile_cap), dim3(PC::NT), 0, s,
+        const RadixDigit dg{(uint32_t)(BITS * p), RADIX - 1};
+        tl.seg_excl = w.seg_excl + (uint64_t)p * L.slot_cap * RADIX;
+        hipLaunchKernelGGL((k_onesweep<K, BITS, PAIRS, RadixDigit, TilesT>), dim3(L.tile_cap), dim3(PC::NT), 0, s,
                            a, dg, tl);
         if (tm) tm->mark(INTSORT_KERNEL_PASS, (uint32_t)p, s);
     }
@@ -486,21 +498,31 @@ static hipError_t seg_run_typed(const SegCall &c, const Src &src, bool separate,
     return hipGetLastError();
 }
 
-hipError_t segmented_sort_run(const SegCall &c, hipStream_t s)
+template <int BITS>
+static hipError_t segmented_sort_bits(const SegCall &c, hipStream_t s)
 {
-    if (c.opts.digit_bits != 8) return hipErrorNotSupported;
     if (c.descs) {
         if (c.pairs) return hipErrorNotSupported;
         const DescSrc src{c.descs};
-        if (c.key_bytes == 4) return seg_run_typed<uint32_t, false, DescSrc, DescTiles>(c, src, true, s);
-        return seg_run_typed<uint64_t, false, DescSrc, DescTiles>(c, src, true, s);
+        if (c.key_bytes == 4) return seg_run_typed<uint32_t, false, DescSrc, DescTiles, BITS>(c, src, true, s);
+        return seg_run_typed<uint64_t, false, DescSrc, DescTiles, BITS>(c, src, true, s);
     }
     const PackedSrc src{c.keys_in, c.keys_out, c.vals_in, c.vals_out, c.offsets};
     if (c.key_bytes == 4)
-        return c.pairs ? seg_run_typed<uint32_t, true, PackedSrc, SegTiles>(c, src, false, s)
-                       : seg_run_typed<uint32_t, false, PackedSrc, SegTiles>(c, src, false, s);
-    return c.pairs ? seg_run_typed<uint64_t, true, PackedSrc, SegTiles>(c, src, false, s)
-                   : seg_run_typed<uint64_t, false, PackedSrc, SegTiles>(c, src, false, s);
+        return c.pairs ? seg_run_typed<uint32_t, true, PackedSrc, SegTiles, BITS>(c, src, false, s)
+                       : seg_run_typed<uint32_t, false, PackedSrc, SegTiles, BITS>(c, src, false, s);
+    return c.pairs ? seg_run_typed<uint64_t, true, PackedSrc, SegTiles, BITS>(c, src, false, s)
+                   : seg_run_typed<uint64_t, false, PackedSrc, SegTiles, BITS>(c, src, false, s);
+}
+
+// The multi-workgroup passes of the large segments take 4- or 8-bit digits
+// (the on-chip classes sort with 8-bit digits whatever the width: any stable
+// sort gives the same bytes).
+hipError_t segmented_sort_run(const SegCall &c, hipStream_t s)
+{
+    if (c.opts.digit_bits == 8) return segmented_sort_bits<8>(c, s);
+    if (c.opts.digit_bits == 4) return segmented_sort_bits<4>(c, s);
+    return hipErrorNotSupported;
 }
 
 }  // namespace intsort

@@ -3,7 +3,7 @@
 // cutoff per device, key width and size class floor(log2 n).
 //
 // The table is a text file, one entry per line, tab-separated:
-//   device key, kind (radix | bucket | segmented), key bytes (4 | 8),
+//   device key, kind (radix | bucket | segmented | segmented_bits), key bytes (4 | 8),
 //   size class, value
 // '#' starts a comment line; '*' as the device key matches every device.
 // Lines that do not parse are skipped, and so are values a call could not
@@ -27,6 +27,7 @@ bool parse_kind(const std::string &s, int *kind)
     if (s == "radix") *kind = TUNE_RADIX_BITS;
     else if (s == "bucket") *kind = TUNE_BUCKETS;
     else if (s == "segmented") *kind = TUNE_LDS_CUTOFF;
+    else if (s == "segmented_bits") *kind = TUNE_SEG_BITS;
     else return false;
     return true;
 }

@@ -8,7 +8,7 @@
 
 namespace intsort {
 
-enum TuneKind { TUNE_RADIX_BITS = 0, TUNE_BUCKETS = 1, TUNE_LDS_CUTOFF = 2 };
+enum TuneKind { TUNE_RADIX_BITS = 0, TUNE_BUCKETS = 1, TUNE_LDS_CUTOFF = 2, TUNE_SEG_BITS = 3 };
 
 struct TuneEntry {
     std::string device;   // device key, or "*" for every device

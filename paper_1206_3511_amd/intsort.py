@@ -349,9 +349,10 @@ def segmented_sort(keys: torch.Tensor, offsets: torch.Tensor, vals: torch.Tensor
     return ok, ov
 
 
-def batched_sort(inputs: list, outputs: list | None = None, stream=None) -> list:
+def batched_sort(inputs: list, outputs: list | None = None, stream=None, **opt) -> list:
     """Sort several separate device arrays (all 32-bit or all 64-bit) in one
-    set of launches; returns the output tensors."""
+    set of launches; returns the output tensors.  `opt` are options
+    (digit_bits, lds_cutoff, flags)."""
     if not inputs:
         return []
     kt = _key_type(inputs[0])
@@ -369,7 +370,7 @@ def batched_sort(inputs: list, outputs: list | None = None, stream=None) -> list
     d_desc = desc.to(dev)
     total = int(sum(t.numel() for t in inputs))
     ctx = context(dev.index)
-    o = make_options("radix")
+    o = make_options("radix", **opt)
     ws = ctx.workspace(ctx.workspace_size(kt, False, total, len(inputs), o), stream)
     _check(lib().intsort_batched_sort_keys(ctx.handle, kt, d_desc.data_ptr(), len(inputs), total, ctypes.byref(o),
                                            ws.data_ptr(), ws.numel(), _stream_ptr(stream)),

@@ -21,11 +21,15 @@ def test_table_roundtrip(tmp_path, monkeypatch):
     assert at.tuned_options("bucket", 4, 100_000_000) == {}
     at._record("radix", 4, 100_000_000, 8, 0, reload=False)                   # replaces the entry
     assert at.load() == [("dev|gfx|hip 1", "radix", 4, 26, 8)]
+    assert at._record("segmented_bits", 4, 1 << 30, 4, 0, reload=False) == {"digit_bits": 4}
+    assert at.tuned_options("segmented_bits", 4, (1 << 30) + 5) == {"digit_bits": 4}
+    assert at.tuned_options("segmented", 4, 1 << 30) == {}
 
 
 def test_candidates_are_supported_options():
     at = importlib.import_module("paper_1206_3511_amd.autotune")
     assert set(at.RADIX_BITS) <= {4, 8, 11}
+    assert set(at.SEG_BITS) <= {4, 8}          # what segmented and batched calls take
     assert max(at.BUCKETS) <= 65536
     assert max(at.CUTOFFS) <= 16384
 

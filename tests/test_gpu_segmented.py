@@ -152,3 +152,67 @@ def test_check_segments_flag_batched():
                 m = r[2]
                 np.testing.assert_array_equal(hb[at:at + m], np.sort(ha[at:at + m]))
                 at += m
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("cutoff", [1, 0])
+def test_four_bit_digits(dtype, pairs, cutoff):
+    """Segmented sorts with 4-bit digits (twice the passes of the longer
+    segments, 16 digits each): the same bytes as the oracle, with every
+    segment on the multi-workgroup path (cutoff 1) or only the long ones,
+    and with keys whose top nibbles are constant (passes skipped)."""
+    offsets = _offsets(BOUNDARY_SIZES)
+    n = int(offsets[-1])
+    for hi in (None, 1 << 20):
+        keys = rand_keys(np.random.default_rng(7), n, dtype, hi=hi)
+        vals = np.arange(n, dtype=np.uint32) if pairs else None
+        ok, ov = _run(keys, offsets, vals, digit_bits=4, lds_cutoff=cutoff)
+        rk, rv = oracle.segmented(keys, offsets, vals)
+        np.testing.assert_array_equal(ok, rk)
+        if pairs:
+            np.testing.assert_array_equal(ov, rv)
+    with pytest.raises(I.IntsortError) as e:
+        _run(keys, offsets, vals, digit_bits=11)
+    assert e.value.status == I.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_four_bit_digits_batched_and_in_place(dtype):
+    sizes = [70_000, 1, 0, 16_385, 300_001, 9000]
+    arrays = [rand_keys(np.random.default_rng(11 + i), m, dtype) for i, m in enumerate(sizes) if m]
+    ins = [dev(a) for a in arrays]
+    outs = I.batched_sort(ins, digit_bits=4, lds_cutoff=2048)
+    for a, o in zip(arrays, outs):
+        np.testing.assert_array_equal(host(o), np.sort(a))
+    offsets = _offsets(sizes)
+    keys = np.concatenate(arrays)
+    offs = torch.from_numpy(offsets.view(np.int64)).to("cuda:0")
+    t = dev(keys)
+    I.segmented_sort(t, offs, out_keys=t, digit_bits=4, lds_cutoff=1)
+    np.testing.assert_array_equal(host(t), oracle.segmented(keys, offsets)[0])
+
+
+def test_tuned_digit_width_is_taken(tmp_path):
+    """A tuning-table entry for segmented digit width 4 makes a call with a
+    zero digit_bits run 4-bit passes (8 launches for 32-bit keys)."""
+    sizes = [100_000, 50_000]
+    offsets = _offsets(sizes)
+    n = int(offsets[-1])
+    keys = rand_keys(np.random.default_rng(3), n, np.uint32)
+    cls = int(np.floor(np.log2(n)))
+    path = tmp_path / "tune.tsv"
+    path.write_text(f"*\tsegmented_bits\t4\t{cls}\t4\n")
+    ctx = I.context(0)
+    offs = torch.from_numpy(offsets.view(np.int64)).to("cuda:0")
+    try:
+        ctx.load_tuning(str(path))
+        ctx.timing(True)
+        ctx.kernel_times()
+        out = I.segmented_sort(dev(keys), offs, lds_cutoff=1)
+        passes = {i for kind, i, _ in ctx.kernel_times() if kind == "pass"}
+    finally:
+        ctx.timing(False)
+        ctx.load_tuning(None)
+    np.testing.assert_array_equal(host(out), oracle.segmented(keys, offsets)[0])
+    assert passes == set(range(8))
