@@ -176,7 +176,7 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
 {
     constexpr int PASSES = 8 * (int)sizeof(K) / BITS;
     constexpr uint32_t RADIX = 1u << BITS;
-    __shared__ uint32_t s_h[PASSES * RADIX];
+    __shared__ uint32_t s_h[(sizeof(K) == 4 && BITS == 8) ? 1 : PASSES * RADIX];
     const uint32_t t = blockIdx.x;
     if (t >= w.counters[CTR_SEG_TILES]) return;
     const TileDesc d = w.tiles[t];
@@ -184,8 +184,64 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
     if (t == d.first_tile)
         for (uint32_t i = threadIdx.x; i < PASSES * RADIX; i += SEG_HIST_THREADS)
             w.seg_excl[((uint64_t)(i / RADIX) * w.slot_cap + d.slot) * RADIX + i % RADIX] = 0;
-    for (uint32_t i = threadIdx.x; i < PASSES * RADIX; i += SEG_HIST_THREADS) s_h[i] = 0;
     for (uint32_t i = threadIdx.x; i < RADIX; i += SEG_HIST_THREADS) w.status0[(uint64_t)t * RADIX + i] = 0;
+    uint32_t *out = w.tile_hist + (uint64_t)t * PASSES * RADIX;
+    if constexpr (sizeof(K) == 4 && BITS == 8) {
+        // 32-bit keys: HC copies of the counts, lane l adding into copy
+        // l % HC, two 16-bit counts to a word (word (p, v / 2, copy) holds
+        // digit value v of pass p in half v % 2): at most a few lanes of an
+        // add meet on a word whatever the keys.  The tile is read as
+        // 16-byte vectors after the keys before the first 16-byte boundary.
+        constexpr int HC = 16, HALF = (int)RADIX / 2;
+        // one copy counts SEG_HIST_THREADS / HC threads' keys of one tile
+        static_assert((uint64_t)PassCfg<K, BITS>::TILE / HC < 65536u, "16-bit counts cannot overflow");
+        __shared__ uint32_t s_c[PASSES * HALF * HC];
+        for (uint32_t i = threadIdx.x; i < (uint32_t)(PASSES * HALF * HC); i += SEG_HIST_THREADS) s_c[i] = 0;
+        __syncthreads();
+        uint32_t *my_c = s_c + threadIdx.x % HC;
+        auto count_key = [&](uint32_t k) {
+#pragma unroll
+            for (int p = 0; p < PASSES; p++) {
+                const uint32_t v = (k >> (BITS * p)) & (RADIX - 1);
+                atomicAdd(my_c + (p * HALF + (v >> 1)) * HC, 1u << (16 * (v & 1)));
+            }
+        };
+        const uint32_t *kt = reinterpret_cast<const uint32_t *>(kp + d.start);
+        const uint32_t head = min(d.count, (uint32_t)((4u - ((uint32_t)(reinterpret_cast<uintptr_t>(kt) >> 2) & 3u)) & 3u));
+        if (threadIdx.x < head) count_key(kt[threadIdx.x]);
+        const uint32_t nv = (d.count - head) / 4;
+        const uint4 *vp = reinterpret_cast<const uint4 *>(kt + head);
+        constexpr int VU = 4;   // vectors in flight per thread
+        for (uint32_t v0 = threadIdx.x; v0 < nv; v0 += SEG_HIST_THREADS * VU) {
+            uint4 x[VU];
+#pragma unroll
+            for (int u = 0; u < VU; u++)
+                if (v0 + u * SEG_HIST_THREADS < nv) x[u] = vp[v0 + u * SEG_HIST_THREADS];
+#pragma unroll
+            for (int u = 0; u < VU; u++) {
+                if (v0 + u * SEG_HIST_THREADS < nv) {
+                    count_key(x[u].x);
+                    count_key(x[u].y);
+                    count_key(x[u].z);
+                    count_key(x[u].w);
+                }
+            }
+        }
+        for (uint32_t i = head + nv * 4 + threadIdx.x; i < d.count; i += SEG_HIST_THREADS) count_key(kt[i]);
+        __syncthreads();
+        // the sum of the copies (read from a rotated start, so that the
+        // threads spread over the banks)
+        for (uint32_t i = threadIdx.x; i < PASSES * RADIX; i += SEG_HIST_THREADS) {
+            const uint32_t p = i / RADIX, v = i % RADIX;
+            const uint32_t *wd = s_c + (p * HALF + (v >> 1)) * HC;
+            uint32_t c = 0;
+#pragma unroll
+            for (int q = 0; q < HC; q++) c += (wd[(q + (v >> 1)) % HC] >> (16 * (v & 1))) & 0xffffu;
+            out[i] = c;
+        }
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < PASSES * RADIX; i += SEG_HIST_THREADS) s_h[i] = 0;
     __syncthreads();
     // U loads in flight per thread (segments start anywhere, so 4- or
     // 8-byte loads)
@@ -207,7 +263,6 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_seg_tile_hist(const K *__r
         }
     }
     __syncthreads();
-    uint32_t *out = w.tile_hist + (uint64_t)t * PASSES * RADIX;
     for (uint32_t i = threadIdx.x; i < PASSES * RADIX; i += SEG_HIST_THREADS) out[i] = s_h[i];
 }
 
