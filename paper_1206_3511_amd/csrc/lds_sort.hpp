@@ -239,9 +239,10 @@ __global__ __launch_bounds__(NT) void k_lds_sort(LdsSortArgs<Src> a)
 // bytes.  Every key's varying bytes go once into byte planes in LDS, and the
 // passes move 16-bit element indices instead of the keys and values: a pass
 // reads one digit byte and writes and reads one index per key, against eight
-// key and four value bytes written and read.  The sorted keys and values are
-// gathered from the segment's input at the end (every gather is done before
-// any store, so the sort may run in place).
+// key and four value bytes written and read.  At the end the keys go back
+// into LDS (where the byte planes were) and the sorted keys are gathered
+// from there, the values from the segment's input (every gather is done
+// before any store, so the sort may run in place).
 template <typename K, bool PAIRS, int NT, int IPT, class Src>
 __global__ __launch_bounds__(NT) void k_lds_sort_idx(LdsSortArgs<Src> a)
 {
@@ -251,7 +252,8 @@ __global__ __launch_bounds__(NT) void k_lds_sort_idx(LdsSortArgs<Src> a)
     constexpr int KB = (int)sizeof(K);
     constexpr int DPT = RADIX > NT ? RADIX / NT : 1;
     static_assert(TILE <= 65536, "16-bit element indices");
-    __shared__ uint8_t s_dig[KB * TILE];    // byte p of element e at s_dig[p * TILE + e]
+    // byte p of element e at s_dig[p * TILE + e]; after the passes, the keys
+    __shared__ alignas(16) uint8_t s_dig[KB * TILE];
     __shared__ uint16_t s_idx[TILE];
     __shared__ uint32_t s_wcnt[WAVES * RADIX];
     __shared__ uint32_t s_excl[RADIX];
@@ -366,11 +368,16 @@ __global__ __launch_bounds__(NT) void k_lds_sort_idx(LdsSortArgs<Src> a)
     // the first m positions hold the real elements in sorted order; every
     // gather completes before the barrier, so no store overwrites a key or
     // value another thread still reads
+    K *s_keys = reinterpret_cast<K *>(s_dig);   // TILE keys fill the planes' bytes
+#pragma unroll
+    for (int j = 0; j < IPT; j++)
+        if (lofs + j * WAVE < m) s_keys[lofs + j * WAVE] = k[j];
+    __syncthreads();
     uint32_t v[PAIRS ? IPT : 1];
 #pragma unroll
     for (int j = 0; j < IPT; j++) {
         if (lofs + j * WAVE < m) {
-            k[j] = kin[e[j]];
+            k[j] = s_keys[e[j]];
             if (PAIRS) v[j] = vin[e[j]];
         }
     }
