@@ -355,6 +355,9 @@ intsort_status intsort_batched_sort_keys(intsort_ctx *ctx, intsort_key_type kt,
  * intsort_server_drain: blocks until every submitted request has finished;
  *   INTSORT_ERR_HIP when a request failed since the previous drain.
  * intsort_server_destroy: drains, stops the worker, frees the workspaces.
+ * submit, poll, completed, drain and fail_next_launches may be called from
+ * several threads at once (the server serialises them); destroy must not
+ * overlap any other call on the same server.
  */
 typedef struct intsort_server intsort_server;
 

@@ -147,3 +147,43 @@ def test_server_failed_launch_reports_and_keeps_serving():
         if t not in srv.failed:
             np.testing.assert_array_equal(host(o), oracle.radix_lsd(a).keys)
     srv.close()
+
+
+def test_server_submit_from_several_threads():
+    """Four host threads submit and poll at once (the server serialises its
+    calls); every request comes back sorted and is reported once."""
+    import threading
+    srv = I.Server(0, budget_bytes=8 << 30, max_batch=16, slots=2)
+    per = 24
+    reqs = [[workloads.config2_keys(i % 7, 1000 + 997 * i + 50_000 * t, 700 + 100 * t + i).astype(np.uint32)
+             for i in range(per)] for t in range(4)]
+    ins = [[dev(a) for a in r] for r in reqs]
+    outs = [[torch.empty_like(x) for x in r] for r in ins]
+    torch.cuda.synchronize()
+    tickets = [[] for _ in range(4)]
+    errors = []
+
+    def work(t):
+        try:
+            for a, b in zip(ins[t], outs[t]):
+                tickets[t].append(srv.submit(a, b))
+            for tk in tickets[t]:
+                while not srv.poll(tk)[0]:
+                    time.sleep(0.0002)
+        except Exception as e:   # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=60)
+    assert not errors and not any(th.is_alive() for th in threads)
+    srv.drain()
+    done = [t for t, _ in srv.completed()]
+    allt = [x for r in tickets for x in r]
+    assert sorted(done) == sorted(allt) and len(set(allt)) == 4 * per
+    for t in range(4):
+        for a, o in zip(reqs[t], outs[t]):
+            np.testing.assert_array_equal(host(o), np.sort(a))
+    srv.close()
