@@ -87,6 +87,8 @@ struct HistArgs {
 };
 
 // PER_TILE: the first pass's digits are counted per tile (a.tile_counts set)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <typename K, int BITS, int ORDER, bool PER_TILE>
 __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__restrict__ keys, HistArgs a)
 {
@@ -159,7 +161,15 @@ __global__ __launch_bounds__(HIST_THREADS) void k_digit_histogram(const K *__res
                 const Vec *tv = reinterpret_cast<const Vec *>(keys + k0) + tid;
                 Vec x[VPTH];
 #pragma unroll
-                for (int j = 0; j < VPTH; j++) x[j] = tv[j * HIST_THREADS];
+                for (int j = 0; j < VPTH; j++) {
+                    // non-temporal: the keys do not take last-level cache
+                    // lines, so the lines the previous kernel left dirty
+                    // there are not evicted (written back) under this read
+                    // (the write-back moves into the first pass, which
+                    // costs less than it saves here)
+                    const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(tv + j * HIST_THREADS));
+                    __builtin_memcpy(&x[j], &t, sizeof(t));
+                }
 #pragma unroll
                 for (int j = 0; j < VPTH; j++)
 #pragma unroll
