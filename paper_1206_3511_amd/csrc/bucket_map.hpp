@@ -10,7 +10,8 @@
 // exact fixed-point product; 64-bit keys take a double-precision estimate
 // that is at most one away from b(k) and one exact remainder check.  Neither
 // branches, so the result is exact for every key and costs the same for every
-// range.
+// range.  The map and the index are host and device functions, so that a host
+// program can check them against exact 128-bit arithmetic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,7 +32,7 @@ struct BucketMap {
     uint32_t r_hi;        // and bits 64..95 (1 when R = 2^64)
 };
 
-__device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, uint32_t B)
+__host__ __device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, uint32_t B)
 {
     BucketMap m;
     m.mn = mn;
@@ -76,10 +77,10 @@ __device__ __forceinline__ BucketMap make_bucket_map(uint64_t mn, uint64_t mx, u
 // (c = 0 gives mul = 1 and 0).  x * mul / 2^64 is taken as
 // (x * mul_hi + floor(x * mul_lo / 2^32)) / 2^32, which fits 64 bits.  A key
 // outside [min, max] (x >= R, also when it lies below min) takes B - 1.
-__device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint32_t k)
+__host__ __device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint32_t k)
 {
     const uint32_t x = k - (uint32_t)m.mn;
-    const uint64_t t = (uint64_t)x * (m.mul >> 32) + __umulhi(x, (uint32_t)m.mul);
+    const uint64_t t = (uint64_t)x * (m.mul >> 32) + (((uint64_t)x * (uint32_t)m.mul) >> 32);
     const uint32_t q = (uint32_t)(t >> 32) + x * m.a32;
     return x <= (uint32_t)m.range_m1 ? q : m.buckets - 1;
 }
@@ -93,7 +94,7 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint32_t k)
 // are below 2^95, and r is taken exactly as a 96-bit two's-complement number
 // (64-bit low part, 32-bit high part) from four 32 x 32 -> 64-bit products.
 // A key outside [min, max] (x >= R, also when it lies below min) takes B - 1.
-__device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint64_t k)
+__host__ __device__ __forceinline__ uint32_t bucket_of(const BucketMap &m, uint64_t k)
 {
     const uint64_t x = k - m.mn;
     const uint32_t B = m.buckets;
