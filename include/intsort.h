@@ -357,7 +357,9 @@ intsort_status intsort_batched_sort_keys(intsort_ctx *ctx, intsort_key_type kt,
  * intsort_server_destroy: drains, stops the worker, frees the workspaces.
  * submit, poll, completed, drain and fail_next_launches may be called from
  * several threads at once (the server serialises them); destroy must not
- * overlap any other call on the same server.
+ * overlap any other call on the same server.  A finished ticket that
+ * completed has listed is forgotten whichever thread submitted it: poll on
+ * it then returns INTSORT_ERR_INVALID_ARGUMENT.
  */
 typedef struct intsort_server intsort_server;
 

@@ -499,8 +499,6 @@ class Server:
                                            ctypes.byref(self.handle)), "intsort_server_create")
         self._live: dict[int, tuple] = {}
         self.failed: set[int] = set()
-        self._buf_t = (_u64 * 4096)()
-        self._buf_l = (ctypes.c_double * 4096)()
 
     def submit(self, keys: torch.Tensor, out: torch.Tensor) -> int:
         _dev_tensor(keys, "keys")
@@ -516,14 +514,16 @@ class Server:
         failed ones included.  Failed tickets go into `failed`; with
         raise_on_failure the call then raises ServerRequestsFailed."""
         res, bad = [], []
+        # buffers of this call (the C calls may run in several threads at once)
+        buf_t, buf_l = (_u64 * 4096)(), (ctypes.c_double * 4096)()
         while True:
             cnt = ctypes.c_uint32(0)
-            rc = lib().intsort_server_completed(self.handle, self._buf_t, self._buf_l, 4096, ctypes.byref(cnt))
+            rc = lib().intsort_server_completed(self.handle, buf_t, buf_l, 4096, ctypes.byref(cnt))
             if rc not in (OK, ERR_HIP):
                 raise IntsortError(rc, "intsort_server_completed")
             for i in range(cnt.value):
-                t = int(self._buf_t[i])
-                res.append((t, float(self._buf_l[i])))
+                t = int(buf_t[i])
+                res.append((t, float(buf_l[i])))
                 self._live.pop(t, None)
                 if rc == ERR_HIP:
                     done = ctypes.c_int(0)

@@ -150,8 +150,9 @@ def test_server_failed_launch_reports_and_keeps_serving():
 
 
 def test_server_submit_from_several_threads():
-    """Four host threads submit and poll at once (the server serialises its
-    calls); every request comes back sorted and is reported once."""
+    """Four host threads submit, poll and collect completions at once (the
+    server serialises its calls); every request comes back sorted and every
+    ticket is reported by exactly one completed() call."""
     import threading
     srv = I.Server(0, budget_bytes=8 << 30, max_batch=16, slots=2)
     per = 24
@@ -161,7 +162,11 @@ def test_server_submit_from_several_threads():
     outs = [[torch.empty_like(x) for x in r] for r in ins]
     torch.cuda.synchronize()
     tickets = [[] for _ in range(4)]
+    reported = [[] for _ in range(4)]
     errors = []
+    # completed() forgets the finished tickets it lists, whichever thread
+    # submitted them: every thread polls its own before any collects them
+    polled = threading.Barrier(4, timeout=60)
 
     def work(t):
         try:
@@ -170,6 +175,8 @@ def test_server_submit_from_several_threads():
             for tk in tickets[t]:
                 while not srv.poll(tk)[0]:
                     time.sleep(0.0002)
+            polled.wait()
+            reported[t].extend(tk for tk, _ in srv.completed())
         except Exception as e:   # reported by the main thread
             errors.append(e)
 
@@ -180,7 +187,7 @@ def test_server_submit_from_several_threads():
         th.join(timeout=60)
     assert not errors and not any(th.is_alive() for th in threads)
     srv.drain()
-    done = [t for t, _ in srv.completed()]
+    done = [t for r in reported for t in r] + [t for t, _ in srv.completed()]
     allt = [x for r in tickets for x in r]
     assert sorted(done) == sorted(allt) and len(set(allt)) == 4 * per
     for t in range(4):
