@@ -62,7 +62,7 @@ typedef INTSORT_ENUM(intsort_status) {
     INTSORT_ERR_INVALID_ARGUMENT = 1, /* null pointer with n > 0, bad enum, overlap */
     INTSORT_ERR_MISALIGNED = 2,       /* a base pointer is not 16-byte aligned */
     INTSORT_ERR_WORKSPACE_TOO_SMALL = 3,
-    INTSORT_ERR_UNSUPPORTED = 4,      /* option value or size this build does not handle */
+    INTSORT_ERR_UNSUPPORTED = 4,      /* option value or size the library does not handle */
     INTSORT_ERR_OVER_BUDGET = 5,      /* serving: a request larger than the whole budget */
     INTSORT_ERR_HIP = 6,              /* a HIP runtime call or kernel launch failed */
     INTSORT_ERR_INTERNAL = 7,
